@@ -1,0 +1,179 @@
+/*
+ * ptmi.h -- C ABI of the MI355X (gfx950) parallel-tempering library for the
+ * 1D long-range q-state Potts ring.
+ *
+ * The method is that of Boer, "GPU-based simulation of the long-range Potts
+ * model via parallel tempering" (Comput. Phys. Commun.):
+ *   section 2, eqs. 1-3   spins s_i in 1..q, H = -sum J_ij delta(s_i, s_j),
+ *                         each unordered pair {i, j} counted once;
+ *   section 2, eqs. 4-7   periodic couplings J*(r) = sum_n |r + nL|^-(1+sigma),
+ *                         evaluated with two Hurwitz zeta values;
+ *   section 3, eq. 8      Metropolis single-spin flips, p = min(1, e^{-beta dE});
+ *   section 3, eq. 9      replica exchange, p = min(1, e^{(E_i-E_j)(beta_i-beta_j)});
+ *   section 4.2           exchange in two stages, pairs (i, i+1) with i even,
+ *                         then with i odd (indices from 0);
+ *   section 5.1, eqs. 10-12  M = (q Nmax/N - 1)/(q - 1), energy and Binder
+ *                         cumulants (this library accumulates the moments).
+ *
+ * Random numbers come from Philox4x32-10 (Salmon et al., SC'11) with key
+ * (lo32(seed), hi32(seed)).  Walker w, sweep n, attempt t (0 <= t < L) uses
+ * counter (t, n, w, 0): site i = mulhi(o0, L), offset k = 1 + mulhi(o1, q-1),
+ * new state b = ((a - 1 + k) mod q) + 1, u = ((o2 << 20 | o3 >> 12) + 1/2) 2^-52,
+ * accepted iff beta dE + ln u < 0.  Exchange step m, stage g, lower slot k uses
+ * counter (k, m, g, 1), u from (o0, o1), accepted iff ln u < (E_k - E_k+1)
+ * (beta_k - beta_k+1).  Initial uniform spins: counter (j, 0, w, 2), s_j = 1 +
+ * mulhi(o0, q).
+ *
+ * Ownership: the caller owns every host array it passes; arrays are read or
+ * written during the call only (T is copied by pt_init).  All device memory
+ * belongs to the context, either allocated by the library or carved from a
+ * caller-provided device workspace (pt_options.workspace) that must stay
+ * valid until pt_free.  Calls on one context are asynchronous on its stream
+ * except where stated; calls on one context must not overlap.
+ *
+ * Errors: every function returns a pt_status; nothing aborts or throws
+ * across the ABI.  pt_last_error() gives a thread-local message for the
+ * last failing call of the calling thread.
+ */
+#ifndef PTMI_H
+#define PTMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PT_OK = 0,
+    PT_EINVAL = -1,   /* an argument is out of range or a pointer is NULL */
+    PT_ENOMEM = -2,   /* device memory or workspace too small */
+    PT_EDEVICE = -3,  /* a HIP call failed, or a kernel reported an error */
+    PT_ESTATE = -4    /* call out of order, or on a freed/failed context */
+} pt_status;
+
+enum { PT_PREC_F64 = 0, PT_PREC_F32 = 1 };
+enum { PT_INIT_RANDOM = 0, PT_INIT_ORDERED = 1 };
+enum { PT_PLACE_AUTO = 0, PT_PLACE_LDS = 1, PT_PLACE_HBM = 2 };
+
+/* Kernel limit on the number of Potts states. */
+#define PT_QMAX 16
+/* Half-width of the band in which two FP64 evaluations of beta dE + ln u may
+ * legitimately disagree in sign; such decisions are logged as events. */
+#define PT_BAND 1e-9
+
+typedef struct {
+    int32_t precision;      /* PT_PREC_F64: FP64 field table; PT_PREC_F32: FP32 table
+                               with FP64 recheck of near-threshold attempts */
+    int32_t init;           /* PT_INIT_RANDOM or PT_INIT_ORDERED (all spins 1) */
+    int32_t placement;      /* where the field table lives during a sweep */
+    int32_t threads;        /* threads per walker workgroup (multiple of 64, <= 1024); 0 = auto */
+    int32_t refresh_every;  /* sweeps between O(L^2) recomputations of the fields; 0 = auto */
+    int32_t series_capacity;/* sweeps of per-slot E and M to keep (0 = none) */
+    int32_t event_capacity; /* entries of the banded-event log (0 = 4096) */
+    int32_t max_sweeps_per_launch; /* 0 = auto */
+    void *stream;           /* hipStream_t to run on, NULL = the null stream */
+    void *workspace;        /* optional caller-owned device memory for all state */
+    size_t workspace_bytes; /* its size; must be >= pt_workspace_size() */
+} pt_options;
+
+/* One near-threshold decision.  kind 0: Metropolis (a = walker, b = sweep,
+ * c = attempt); kind 1: exchange (a = exchange step, b = stage, c = lower
+ * slot).  x is the FP64 value of beta dE + ln u (kind 0) or ln u - Delta
+ * (kind 1); decision is 1 for accepted. */
+typedef struct {
+    int64_t a, b, c;
+    int32_t kind, decision;
+    double x;
+} pt_event;
+
+/* Observables.  Every pointer may be NULL (skipped); arrays are caller-owned
+ * host memory of the stated length.  "by slot" = by temperature index k,
+ * T ascending as passed to pt_init. */
+typedef struct {
+    int32_t R, q, L;          /* out */
+    int64_t sweeps;           /* sweeps done since pt_init */
+    int64_t exchange_steps;   /* exchange steps done since pt_init */
+    int64_t samples;          /* sweeps accumulated since the last pt_reset_stats */
+    double *E, *M;            /* [R] current energy and magnetisation by slot */
+    double *sumE, *sumE2, *sumE4, *sumM, *sumM2, *sumM4; /* [R] FP64 moments by slot */
+    int64_t *flip_att, *flip_acc; /* [R] Metropolis attempts / accepts by slot */
+    int64_t *xchg_att, *xchg_acc; /* [R-1] exchange attempts / accepts, pair (k, k+1) */
+    int32_t *perm;            /* [R] slot -> walker */
+    int64_t n_recheck;        /* FP64 direct rechecks of near-threshold attempts */
+    int64_t n_banded;         /* decisions inside PT_BAND (Metropolis + exchange) */
+    int64_t n_exact_energy;   /* exact O(L^2) energies computed for uncertain exchanges */
+    int64_t n_refresh;        /* field recomputations */
+    int64_t n_events_dropped; /* events beyond event_capacity */
+} pt_obs;
+
+typedef struct pt_ctx pt_ctx;
+
+/* Fills *opt with defaults (FP64 table, random init, auto placement). */
+void pt_default_options(pt_options *opt);
+
+/* Device bytes pt_init needs for (L, q, R, opt); opt may be NULL. */
+pt_status pt_workspace_size(int32_t L, int32_t q, int32_t R, const pt_options *opt, size_t *bytes);
+
+/* Creates a run: computes J*(r) on the GPU (eq. 6, FP64), draws the initial
+ * spins, builds the field table and the energies, sets perm = identity.
+ *   L >= 2; 2 <= q <= PT_QMAX; sigma > 0 (zeta(1+sigma) diverges at 0);
+ *   T[R] > 0, finite, ascending (slot k has temperature T[k]); R >= 1.
+ * On success *out owns the device state; the work is queued on the stream. */
+pt_status pt_init(pt_ctx **out, int32_t L, int32_t q, double sigma, const double *T, int32_t R,
+                  uint64_t seed, const pt_options *opt);
+
+/* n sweeps of L Metropolis attempts per walker (eq. 8), observables
+ * recorded per slot after each sweep, no exchange.  Asynchronous. */
+pt_status pt_sweep(pt_ctx *ctx, int64_t n);
+
+/* One exchange step (eq. 9): even stage then odd stage.  Asynchronous. */
+pt_status pt_exchange(pt_ctx *ctx);
+
+/* n sweeps with an exchange step after every exchange_every-th sweep, in
+ * persistent cooperative launches with a device-side grid barrier (no host
+ * round trip per sweep).  exchange_every = 0 behaves like pt_sweep.
+ * Asynchronous. */
+pt_status pt_run(pt_ctx *ctx, int64_t n, int32_t exchange_every);
+
+/* Waits for queued work and copies observables to the host.  Synchronising. */
+pt_status pt_observables(pt_ctx *ctx, pt_obs *out);
+
+/* Spins by walker [R][L], values 1..q, and perm [R] (either may be NULL).
+ * Synchronising. */
+pt_status pt_get_spins(pt_ctx *ctx, uint8_t *spins_out, int32_t *perm_out);
+
+/* J*(r), r = 0..L-1, as computed on the GPU (FP64).  Synchronising. */
+pt_status pt_get_jstar(pt_ctx *ctx, double *out);
+
+/* Per-sweep E and M by slot, [n][R] each, for the first min(recorded,
+ * capacity) sweeps since pt_init; *n_out receives the row count. */
+pt_status pt_get_series(pt_ctx *ctx, double *E, double *M, int64_t cap_rows, int64_t *n_out);
+
+/* Logged near-threshold events (up to cap); *n_out receives the count stored. */
+pt_status pt_get_events(pt_ctx *ctx, pt_event *out, int64_t cap, int64_t *n_out);
+
+/* Zeroes the moment and acceptance accumulators (e.g. after burn-in). */
+pt_status pt_reset_stats(pt_ctx *ctx);
+
+/* Blocks until all queued work of the context has finished; reports device
+ * errors raised by kernels (e.g. a grid-barrier time-out). */
+pt_status pt_synchronize(pt_ctx *ctx);
+
+/* Checkpoint: the complete state is (spins, perm, sweep and exchange
+ * counters, accumulators, seed, parameters); fields are rebuilt on load.
+ * pt_save with buf == NULL returns the needed size in *len. */
+pt_status pt_save(pt_ctx *ctx, void *buf, size_t *len);
+pt_status pt_load(pt_ctx **out, const void *buf, size_t len, const pt_options *opt);
+
+/* Releases device memory (not a caller workspace) and the context. */
+pt_status pt_free(pt_ctx *ctx);
+
+/* Thread-local message of the last failure on this thread ("" if none). */
+const char *pt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PTMI_H */

@@ -1,0 +1,656 @@
+// ptmi.hip -- host runtime and C ABI of the gfx950 parallel-tempering library
+// for the 1D long-range q-state Potts ring (see include/ptmi.h for the
+// contract of every entry point and the paper passages they implement).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ptmi.h"
+#include "sweep.hpp"
+
+using namespace ptmi;
+
+static_assert(sizeof(pt_event) == sizeof(Event), "event layout");
+static_assert(PT_QMAX == kQMax, "q limit");
+
+namespace {
+
+thread_local std::string g_err;
+
+pt_status fail(pt_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return fail(PT_EDEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                                          __FILE__, __LINE__);                                    \
+    } while (0)
+
+constexpr uint32_t kMagic = 0x50544d49u;  // "PTMI"
+constexpr uint32_t kVersion = 1;
+
+}  // namespace
+
+struct pt_ctx {
+    int32_t L = 0, q = 0, R = 0, prec = 0, init = 0, NT = 64, refresh_every = 0, ser_cap = 0,
+            ev_cap = 0, max_chunk = 0, device = 0, cus = 0;
+    double sigma = 0.0;
+    uint64_t seed = 0;
+    hipStream_t stream = nullptr;
+    unsigned char *ws = nullptr;
+    size_t ws_bytes = 0;
+    bool own_ws = false;
+    bool failed = false;
+    Inst inst{};
+    LdsPlan plan{}, plan_fused{};
+    bool can_fuse = false;
+    int64_t sweeps = 0, xsteps = 0, samples = 0;
+    std::vector<double> T;
+};
+
+namespace {
+
+size_t field_bytes(int prec) { return prec == PT_PREC_F32 ? sizeof(float) : sizeof(double); }
+
+int auto_threads(int L)
+{
+    const int waves = std::min(16, std::max(1, (L + 255) / 256));
+    return waves * kWave;
+}
+
+int32_t align16(int32_t x) { return (x + 15) & ~15; }
+
+// LDS carve: couplings, field table, FP64 couplings (if they fit), per-state
+// site masks, spins, counts, reduction scratch, flags, exchange scratch.
+bool make_plan(int L, int q, int R, int prec, bool fused, size_t lds_max, LdsPlan *p)
+{
+    const int32_t fb = static_cast<int32_t>(field_bytes(prec));
+    const int nblk = (L + kWave - 1) / kWave;
+    int32_t o = 0;
+    p->J = o; o = align16(o + fb * L);
+    p->h = o; o = align16(o + fb * q * L);
+    p->masks = o; o = align16(o + 8 * q * nblk);
+    p->sp = o; o = align16(o + L);
+    p->cnt = o; o = align16(o + 4 * kQMax);
+    p->red = o; o = align16(o + 8 * 32);
+    p->misc = o; o = align16(o + 4 * 8);
+    p->xch = o;
+    if (fused) o = align16(o + 40 * R);
+    if (prec == PT_PREC_F64) {
+        p->J64 = p->J;
+        p->j64_in_lds = 1;
+    } else if (static_cast<size_t>(o) + 8u * L <= lds_max) {
+        p->J64 = o;
+        o = align16(o + 8 * L);
+        p->j64_in_lds = 1;
+    } else {
+        p->J64 = 0;
+        p->j64_in_lds = 0;
+    }
+    p->total = o;
+    return static_cast<size_t>(o) <= lds_max;
+}
+
+Layout layout_of(int L, int q, int R, int prec, int ser_cap, int ev_cap)
+{
+    return Layout(L, q, R, field_bytes(prec), ser_cap, ev_cap);
+}
+
+pt_status validate(int32_t L, int32_t q, double sigma, const double *T, int32_t R)
+{
+    if (L < 2) return fail(PT_EINVAL, "L must be >= 2 (got %d)", L);
+    if (q < 2 || q > PT_QMAX) return fail(PT_EINVAL, "q must be in [2, %d] (got %d)", PT_QMAX, q);
+    if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(PT_EINVAL, "sigma must be finite and > 0");
+    if (R < 1) return fail(PT_EINVAL, "R must be >= 1");
+    if (!T) return fail(PT_EINVAL, "T is NULL");
+    for (int k = 0; k < R; ++k) {
+        if (!(T[k] > 0.0) || !std::isfinite(T[k])) return fail(PT_EINVAL, "T[%d] must be finite and > 0", k);
+        if (k > 0 && T[k] < T[k - 1]) return fail(PT_EINVAL, "T must be ascending (T[%d] < T[%d])", k, k - 1);
+    }
+    return PT_OK;
+}
+
+template <typename F>
+const void *sweep_fn() { return reinterpret_cast<const void *>(&k_sweep<F>); }
+template <typename F>
+const void *refresh_fn() { return reinterpret_cast<const void *>(&k_refresh<F>); }
+
+pt_status set_lds_attr(const void *fn, int bytes)
+{
+    HIPCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+    return PT_OK;
+}
+
+template <typename F>
+pt_status launch_refresh(pt_ctx *c)
+{
+    hipLaunchKernelGGL(k_refresh<F>, dim3(c->R), dim3(c->NT), c->plan.total, c->stream, c->inst, c->plan);
+    HIPCHK(hipGetLastError());
+    return PT_OK;
+}
+
+template <typename F>
+pt_status launch_sweep(pt_ctx *c, int64_t n0, int32_t nsw, int32_t xevery, int64_t m0, bool fused)
+{
+    if (fused) {
+        Inst P = c->inst;
+        LdsPlan plan = c->plan_fused;
+        int32_t fu = 1;
+        void *args[] = {&P, &plan, &n0, &nsw, &xevery, &m0, &fu};
+        HIPCHK(hipLaunchCooperativeKernel(sweep_fn<F>(), dim3(c->R), dim3(c->NT), args, plan.total, c->stream));
+    } else {
+        hipLaunchKernelGGL(k_sweep<F>, dim3(c->R), dim3(c->NT), c->plan.total, c->stream, c->inst, c->plan, n0,
+                           nsw, xevery, m0, 0);
+        HIPCHK(hipGetLastError());
+    }
+    return PT_OK;
+}
+
+pt_status launch_exchange(pt_ctx *c)
+{
+    const int bytes = 256 + 40 * c->R;
+    hipLaunchKernelGGL(k_exchange, dim3(1), dim3(std::min(1024, std::max(64, ((c->R + 63) / 64) * 64))),
+                       bytes, c->stream, c->inst, c->xsteps);
+    HIPCHK(hipGetLastError());
+    return PT_OK;
+}
+
+pt_status check_ctx(pt_ctx *c)
+{
+    if (!c) return fail(PT_EINVAL, "null context");
+    if (c->failed) return fail(PT_ESTATE, "context is in a failed state");
+    return PT_OK;
+}
+
+pt_status device_error(pt_ctx *c)
+{
+    unsigned long long err = 0;
+    HIPCHK(hipMemcpy(&err, c->inst.ctr + kCtrError, sizeof err, hipMemcpyDeviceToHost));
+    if (err) {
+        c->failed = true;
+        return fail(PT_EDEVICE, "kernel reported error bits 0x%llx (grid barrier time-out)", err);
+    }
+    return PT_OK;
+}
+
+// Rigorous per-entry bounds of the field table (see the design notes): right
+// after a refresh the FP64 sum of at most L terms is rounded to the table's
+// precision; each applied flip adds one rounded coupling and one rounding.
+void set_bounds(pt_ctx *c, const std::vector<double> &J)
+{
+    double S = 0.0, Jmax = 0.0;
+    for (double v : J) {
+        S += v;
+        Jmax = std::max(Jmax, v);
+    }
+    const double u64 = std::ldexp(1.0, -53);
+    const double uF = c->prec == PT_PREC_F32 ? std::ldexp(1.0, -24) : u64;
+    const double L = c->L;
+    c->inst.bound_init = (uF * S + (L + 4.0) * u64 * S) * 1.01 + 1e-15 * S;
+    c->inst.bound_unit = uF * (1.001 * S + 2.0 * Jmax) * 1.01 + u64 * S;
+    const double cap = 1e-3 * S / c->inst.bound_unit;
+    c->inst.nupd_max = cap > 4.0e18 ? static_cast<int64_t>(4e18) : static_cast<int64_t>(cap);
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+void pt_default_options(pt_options *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->precision = PT_PREC_F64;
+    o->init = PT_INIT_RANDOM;
+    o->placement = PT_PLACE_AUTO;
+}
+
+const char *pt_last_error(void) { return g_err.c_str(); }
+
+pt_status pt_workspace_size(int32_t L, int32_t q, int32_t R, const pt_options *opt, size_t *bytes)
+{
+    if (!bytes) return fail(PT_EINVAL, "bytes is NULL");
+    if (L < 2 || q < 2 || q > PT_QMAX || R < 1) return fail(PT_EINVAL, "bad sizes");
+    pt_options d;
+    pt_default_options(&d);
+    const pt_options &o = opt ? *opt : d;
+    const int ev = o.event_capacity > 0 ? o.event_capacity : 4096;
+    *bytes = layout_of(L, q, R, o.precision, std::max(0, o.series_capacity), ev).total;
+    return PT_OK;
+}
+
+static pt_status init_impl(pt_ctx **out, int32_t L, int32_t q, double sigma, const double *T, int32_t R,
+                           uint64_t seed, const pt_options *opt, bool draw_spins)
+{
+    pt_options d;
+    pt_default_options(&d);
+    const pt_options &o = opt ? *opt : d;
+    if (o.precision != PT_PREC_F64 && o.precision != PT_PREC_F32) return fail(PT_EINVAL, "bad precision");
+    if (o.init != PT_INIT_RANDOM && o.init != PT_INIT_ORDERED) return fail(PT_EINVAL, "bad init");
+    if (o.threads && (o.threads % kWave || o.threads < kWave || o.threads > 1024))
+        return fail(PT_EINVAL, "threads must be a multiple of 64 in [64, 1024]");
+    if (o.placement == PT_PLACE_HBM) return fail(PT_EINVAL, "HBM field placement is not available in this build");
+
+    pt_ctx *c = new (std::nothrow) pt_ctx();
+    if (!c) return fail(PT_ENOMEM, "host allocation failed");
+    c->L = L; c->q = q; c->R = R; c->prec = o.precision; c->init = o.init; c->sigma = sigma; c->seed = seed;
+    c->NT = o.threads ? o.threads : auto_threads(L);
+    c->ser_cap = std::max(0, o.series_capacity);
+    c->ev_cap = o.event_capacity > 0 ? o.event_capacity : 4096;
+    c->stream = static_cast<hipStream_t>(o.stream);
+    c->T.assign(T, T + R);
+    auto bail = [&](pt_status st) {
+        if (c->own_ws && c->ws) (void)hipFree(c->ws);
+        delete c;
+        return st;
+    };
+
+    if (hipGetDevice(&c->device) != hipSuccess) return bail(fail(PT_EDEVICE, "no HIP device"));
+    int lds_max = 0;
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess ||
+        hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess)
+        return bail(fail(PT_EDEVICE, "device query failed"));
+    if (!make_plan(L, q, R, c->prec, false, static_cast<size_t>(lds_max), &c->plan))
+        return bail(fail(PT_EINVAL, "field table of %d x %d entries does not fit in %d B of LDS", q, L, lds_max));
+    const bool fused_fits = make_plan(L, q, R, c->prec, true, static_cast<size_t>(lds_max), &c->plan_fused);
+
+    const Layout lay = layout_of(L, q, R, c->prec, c->ser_cap, c->ev_cap);
+    if (o.workspace) {
+        if (o.workspace_bytes < lay.total)
+            return bail(fail(PT_ENOMEM, "workspace of %zu B < %zu B needed", o.workspace_bytes, lay.total));
+        c->ws = static_cast<unsigned char *>(o.workspace);
+        c->ws_bytes = o.workspace_bytes;
+    } else {
+        if (hipMalloc(&c->ws, lay.total) != hipSuccess) return bail(fail(PT_ENOMEM, "hipMalloc(%zu) failed", lay.total));
+        c->own_ws = true;
+        c->ws_bytes = lay.total;
+    }
+    unsigned char *b = c->ws;
+    Inst &P = c->inst;
+    P.L = L; P.q = q; P.R = R; P.walker0 = 0;
+    P.key0 = static_cast<uint32_t>(seed);
+    P.key1 = static_cast<uint32_t>(seed >> 32);
+    P.refresh_every = o.refresh_every > 0 ? o.refresh_every : (c->prec == PT_PREC_F32 ? 32 : 0);
+    c->refresh_every = P.refresh_every;
+    P.ser_cap = c->ser_cap;
+    P.J64 = reinterpret_cast<const double *>(b + lay.J64);
+    P.J32 = reinterpret_cast<const float *>(b + lay.J32);
+    P.spins = b + lay.spins;
+    P.h = b + lay.h;
+    P.E = reinterpret_cast<double *>(b + lay.E);
+    P.Eerr = reinterpret_cast<double *>(b + lay.Eerr);
+    P.nupd = reinterpret_cast<int64_t *>(b + lay.nupd);
+    P.counts = reinterpret_cast<int32_t *>(b + lay.counts);
+    P.Mw = reinterpret_cast<double *>(b + lay.Mw);
+    P.perm = reinterpret_cast<int32_t *>(b + lay.perm);
+    P.slot_of = reinterpret_cast<int32_t *>(b + lay.slot_of);
+    P.beta = reinterpret_cast<const double *>(b + lay.beta);
+    P.acc6 = reinterpret_cast<double *>(b + lay.acc6);
+    P.fatt = reinterpret_cast<int64_t *>(b + lay.fatt);
+    P.facc = reinterpret_cast<int64_t *>(b + lay.facc);
+    P.xatt = reinterpret_cast<int64_t *>(b + lay.xatt);
+    P.xacc = reinterpret_cast<int64_t *>(b + lay.xacc);
+    P.serE = reinterpret_cast<double *>(b + lay.serE);
+    P.serM = reinterpret_cast<double *>(b + lay.serM);
+    P.events = reinterpret_cast<Event *>(b + lay.events);
+    P.ev_cap = c->ev_cap;
+    P.ctr = reinterpret_cast<unsigned long long *>(b + lay.ctr);
+
+    // hipMemset on the (possibly caller-provided) workspace: zero counters,
+    // accumulators and the barrier words.
+    if (hipMemsetAsync(c->ws, 0, lay.total, c->stream) != hipSuccess) return bail(fail(PT_EDEVICE, "memset failed"));
+    std::vector<double> beta(R);
+    std::vector<int32_t> ident(R);
+    for (int k = 0; k < R; ++k) {
+        beta[k] = 1.0 / T[k];
+        ident[k] = k;
+    }
+    if (hipMemcpyAsync(const_cast<double *>(P.beta), beta.data(), sizeof(double) * R, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(P.perm, ident.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(P.slot_of, ident.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+        return bail(fail(PT_EDEVICE, "copy of ladder failed"));
+
+    const void *sf = c->prec == PT_PREC_F32 ? sweep_fn<float>() : sweep_fn<double>();
+    const void *rf = c->prec == PT_PREC_F32 ? refresh_fn<float>() : refresh_fn<double>();
+    const int lds_need = std::max(c->plan.total, fused_fits ? c->plan_fused.total : 0);
+    if (set_lds_attr(sf, lds_need) != PT_OK || set_lds_attr(rf, c->plan.total) != PT_OK) return bail(PT_EDEVICE);
+    if (fused_fits) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sf, c->NT, c->plan_fused.total) == hipSuccess)
+            c->can_fuse = static_cast<int64_t>(per_cu) * c->cus >= R;
+    }
+    c->max_chunk = o.max_sweeps_per_launch > 0 ? o.max_sweeps_per_launch : 1024;
+
+    hipLaunchKernelGGL(k_jstar, dim3((L / 2 + 1 + 255) / 256), dim3(256), 0, c->stream, L, sigma,
+                       const_cast<double *>(P.J64), const_cast<float *>(P.J32));
+    if (hipGetLastError() != hipSuccess) return bail(fail(PT_EDEVICE, "k_jstar launch failed"));
+    if (draw_spins) {
+        const int64_t total = static_cast<int64_t>(R) * L;
+        const int blocks = static_cast<int>(std::min<int64_t>(4096, (total + 255) / 256));
+        hipLaunchKernelGGL(k_init_spins, dim3(blocks), dim3(256), 0, c->stream, P,
+                           static_cast<int32_t>(c->init == PT_INIT_ORDERED));
+        if (hipGetLastError() != hipSuccess) return bail(fail(PT_EDEVICE, "k_init_spins launch failed"));
+        const pt_status st = c->prec == PT_PREC_F32 ? launch_refresh<float>(c) : launch_refresh<double>(c);
+        if (st != PT_OK) return bail(st);
+    }
+    std::vector<double> J(L);
+    if (hipMemcpyAsync(J.data(), P.J64, sizeof(double) * L, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return bail(fail(PT_EDEVICE, "initialisation failed"));
+    for (int r = 0; r < L; ++r)
+        if (!std::isfinite(J[r])) return bail(fail(PT_EDEVICE, "non-finite coupling J*(%d)", r));
+    set_bounds(c, J);
+    *out = c;
+    return PT_OK;
+}
+
+pt_status pt_init(pt_ctx **out, int32_t L, int32_t q, double sigma, const double *T, int32_t R, uint64_t seed,
+                  const pt_options *opt)
+{
+    if (!out) return fail(PT_EINVAL, "out is NULL");
+    *out = nullptr;
+    const pt_status v = validate(L, q, sigma, T, R);
+    if (v != PT_OK) return v;
+    return init_impl(out, L, q, sigma, T, R, seed, opt, true);
+}
+
+pt_status pt_sweep(pt_ctx *c, int64_t n)
+{
+    pt_status st = check_ctx(c);
+    if (st != PT_OK) return st;
+    if (n < 0) return fail(PT_EINVAL, "n < 0");
+    while (n > 0) {
+        const int32_t chunk = static_cast<int32_t>(std::min<int64_t>(n, c->max_chunk));
+        st = c->prec == PT_PREC_F32 ? launch_sweep<float>(c, c->sweeps, chunk, 0, c->xsteps, false)
+                                    : launch_sweep<double>(c, c->sweeps, chunk, 0, c->xsteps, false);
+        if (st != PT_OK) return st;
+        c->sweeps += chunk;
+        c->samples += chunk;
+        n -= chunk;
+    }
+    return PT_OK;
+}
+
+pt_status pt_exchange(pt_ctx *c)
+{
+    pt_status st = check_ctx(c);
+    if (st != PT_OK) return st;
+    st = launch_exchange(c);
+    if (st != PT_OK) return st;
+    c->xsteps += 1;
+    return PT_OK;
+}
+
+pt_status pt_run(pt_ctx *c, int64_t n, int32_t every)
+{
+    pt_status st = check_ctx(c);
+    if (st != PT_OK) return st;
+    if (n < 0 || every < 0) return fail(PT_EINVAL, "n and exchange_every must be >= 0");
+    if (every == 0) return pt_sweep(c, n);
+    if (!c->can_fuse) {
+        for (int64_t s = 0; s < n; ++s) {
+            if ((st = pt_sweep(c, 1)) != PT_OK) return st;
+            if ((c->sweeps % every) == 0 && (st = pt_exchange(c)) != PT_OK) return st;
+        }
+        return PT_OK;
+    }
+    while (n > 0) {
+        // chunks hold whole exchange periods so the schedule is the same as unfused
+        int64_t chunk = std::min<int64_t>(n, c->max_chunk);
+        if (chunk >= every) chunk -= chunk % every;
+        const int64_t nx = chunk / every;
+        st = c->prec == PT_PREC_F32 ? launch_sweep<float>(c, c->sweeps, static_cast<int32_t>(chunk), every, c->xsteps, true)
+                                    : launch_sweep<double>(c, c->sweeps, static_cast<int32_t>(chunk), every, c->xsteps, true);
+        if (st != PT_OK) return st;
+        c->sweeps += chunk;
+        c->samples += chunk;
+        c->xsteps += nx;
+        n -= chunk;
+    }
+    return PT_OK;
+}
+
+pt_status pt_synchronize(pt_ctx *c)
+{
+    if (!c) return fail(PT_EINVAL, "null context");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return device_error(c);
+}
+
+pt_status pt_observables(pt_ctx *c, pt_obs *o)
+{
+    pt_status st = check_ctx(c);
+    if (st != PT_OK) return st;
+    if (!o) return fail(PT_EINVAL, "obs is NULL");
+    if ((st = pt_synchronize(c)) != PT_OK) return st;
+    const int R = c->R;
+    const Inst &P = c->inst;
+    std::vector<double> Ew(R), Mw(R), acc6(6 * R);
+    std::vector<int32_t> perm(R);
+    std::vector<int64_t> fatt(R), facc(R), xatt(R), xacc(R);
+    std::vector<unsigned long long> ctr(kCtrN);
+    HIPCHK(hipMemcpy(Ew.data(), P.E, sizeof(double) * R, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(Mw.data(), P.Mw, sizeof(double) * R, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(acc6.data(), P.acc6, sizeof(double) * 6 * R, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(perm.data(), P.perm, sizeof(int32_t) * R, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(fatt.data(), P.fatt, sizeof(int64_t) * R, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(facc.data(), P.facc, sizeof(int64_t) * R, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(xatt.data(), P.xatt, sizeof(int64_t) * R, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(xacc.data(), P.xacc, sizeof(int64_t) * R, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(ctr.data(), P.ctr, sizeof(unsigned long long) * kCtrN, hipMemcpyDeviceToHost));
+    o->R = R; o->q = c->q; o->L = c->L;
+    o->sweeps = c->sweeps; o->exchange_steps = c->xsteps; o->samples = c->samples;
+    for (int k = 0; k < R; ++k) {
+        if (o->E) o->E[k] = Ew[perm[k]];
+        if (o->M) o->M[k] = Mw[perm[k]];
+        double *dst[6] = {o->sumE, o->sumE2, o->sumE4, o->sumM, o->sumM2, o->sumM4};
+        for (int a = 0; a < 6; ++a)
+            if (dst[a]) dst[a][k] = acc6[a * R + k];
+        if (o->flip_att) o->flip_att[k] = fatt[k];
+        if (o->flip_acc) o->flip_acc[k] = facc[k];
+        if (o->perm) o->perm[k] = perm[k];
+        if (k + 1 < R) {
+            if (o->xchg_att) o->xchg_att[k] = xatt[k];
+            if (o->xchg_acc) o->xchg_acc[k] = xacc[k];
+        }
+    }
+    o->n_recheck = static_cast<int64_t>(ctr[kCtrRecheck]);
+    o->n_banded = static_cast<int64_t>(ctr[kCtrBandedMet] + ctr[kCtrBandedEx]);
+    o->n_exact_energy = static_cast<int64_t>(ctr[kCtrExactE]);
+    o->n_refresh = static_cast<int64_t>(ctr[kCtrRefresh]);
+    o->n_events_dropped = ctr[kCtrEvents] > static_cast<unsigned long long>(c->ev_cap)
+                              ? static_cast<int64_t>(ctr[kCtrEvents] - c->ev_cap)
+                              : 0;
+    return PT_OK;
+}
+
+pt_status pt_get_spins(pt_ctx *c, uint8_t *spins, int32_t *perm)
+{
+    pt_status st = check_ctx(c);
+    if (st != PT_OK) return st;
+    if ((st = pt_synchronize(c)) != PT_OK) return st;
+    const size_t n = static_cast<size_t>(c->R) * c->L;
+    if (spins) {
+        HIPCHK(hipMemcpy(spins, c->inst.spins, n, hipMemcpyDeviceToHost));
+        for (size_t e = 0; e < n; ++e) spins[e] = static_cast<uint8_t>(spins[e] + 1);
+    }
+    if (perm) HIPCHK(hipMemcpy(perm, c->inst.perm, sizeof(int32_t) * c->R, hipMemcpyDeviceToHost));
+    return PT_OK;
+}
+
+pt_status pt_get_jstar(pt_ctx *c, double *out)
+{
+    pt_status st = check_ctx(c);
+    if (st != PT_OK) return st;
+    if (!out) return fail(PT_EINVAL, "out is NULL");
+    if ((st = pt_synchronize(c)) != PT_OK) return st;
+    HIPCHK(hipMemcpy(out, c->inst.J64, sizeof(double) * c->L, hipMemcpyDeviceToHost));
+    return PT_OK;
+}
+
+pt_status pt_get_series(pt_ctx *c, double *E, double *M, int64_t cap_rows, int64_t *n_out)
+{
+    pt_status st = check_ctx(c);
+    if (st != PT_OK) return st;
+    if ((st = pt_synchronize(c)) != PT_OK) return st;
+    const int64_t rows = std::min<int64_t>(std::min<int64_t>(c->sweeps, c->ser_cap), std::max<int64_t>(cap_rows, 0));
+    const size_t bytes = sizeof(double) * static_cast<size_t>(rows) * c->R;
+    if (E && rows) HIPCHK(hipMemcpy(E, c->inst.serE, bytes, hipMemcpyDeviceToHost));
+    if (M && rows) HIPCHK(hipMemcpy(M, c->inst.serM, bytes, hipMemcpyDeviceToHost));
+    if (n_out) *n_out = rows;
+    return PT_OK;
+}
+
+pt_status pt_get_events(pt_ctx *c, pt_event *out, int64_t cap, int64_t *n_out)
+{
+    pt_status st = check_ctx(c);
+    if (st != PT_OK) return st;
+    if ((st = pt_synchronize(c)) != PT_OK) return st;
+    unsigned long long n = 0;
+    HIPCHK(hipMemcpy(&n, c->inst.ctr + kCtrEvents, sizeof n, hipMemcpyDeviceToHost));
+    const int64_t stored = std::min<int64_t>(std::min<int64_t>(static_cast<int64_t>(n), c->ev_cap), std::max<int64_t>(cap, 0));
+    if (out && stored) HIPCHK(hipMemcpy(out, c->inst.events, sizeof(pt_event) * stored, hipMemcpyDeviceToHost));
+    if (n_out) *n_out = stored;
+    return PT_OK;
+}
+
+pt_status pt_reset_stats(pt_ctx *c)
+{
+    pt_status st = check_ctx(c);
+    if (st != PT_OK) return st;
+    const Inst &P = c->inst;
+    HIPCHK(hipMemsetAsync(P.acc6, 0, sizeof(double) * 6 * c->R, c->stream));
+    HIPCHK(hipMemsetAsync(P.fatt, 0, sizeof(int64_t) * c->R, c->stream));
+    HIPCHK(hipMemsetAsync(P.facc, 0, sizeof(int64_t) * c->R, c->stream));
+    HIPCHK(hipMemsetAsync(P.xatt, 0, sizeof(int64_t) * c->R, c->stream));
+    HIPCHK(hipMemsetAsync(P.xacc, 0, sizeof(int64_t) * c->R, c->stream));
+    c->samples = 0;
+    return PT_OK;
+}
+
+// Checkpoint: header, T, spins (0-based), perm, accumulators.
+struct SaveHeader {
+    uint32_t magic, version;
+    int32_t L, q, R, prec, init, refresh_every;
+    uint64_t seed;
+    double sigma;
+    int64_t sweeps, xsteps, samples;
+};
+
+pt_status pt_save(pt_ctx *c, void *buf, size_t *len)
+{
+    pt_status st = check_ctx(c);
+    if (st != PT_OK) return st;
+    if (!len) return fail(PT_EINVAL, "len is NULL");
+    const int R = c->R, L = c->L;
+    const size_t need = sizeof(SaveHeader) + sizeof(double) * R + static_cast<size_t>(R) * L + sizeof(int32_t) * R +
+                        sizeof(double) * 6 * R + sizeof(int64_t) * 4 * R;
+    if (!buf) {
+        *len = need;
+        return PT_OK;
+    }
+    if (*len < need) return fail(PT_EINVAL, "buffer of %zu B < %zu B", *len, need);
+    if ((st = pt_synchronize(c)) != PT_OK) return st;
+    unsigned char *p = static_cast<unsigned char *>(buf);
+    SaveHeader hd{kMagic, kVersion, L, c->q, R, c->prec, c->init, c->refresh_every, c->seed, c->sigma,
+                  c->sweeps, c->xsteps, c->samples};
+    std::memcpy(p, &hd, sizeof hd); p += sizeof hd;
+    std::memcpy(p, c->T.data(), sizeof(double) * R); p += sizeof(double) * R;
+    const Inst &P = c->inst;
+    HIPCHK(hipMemcpy(p, P.spins, static_cast<size_t>(R) * L, hipMemcpyDeviceToHost)); p += static_cast<size_t>(R) * L;
+    HIPCHK(hipMemcpy(p, P.perm, sizeof(int32_t) * R, hipMemcpyDeviceToHost)); p += sizeof(int32_t) * R;
+    HIPCHK(hipMemcpy(p, P.acc6, sizeof(double) * 6 * R, hipMemcpyDeviceToHost)); p += sizeof(double) * 6 * R;
+    int64_t *arrs[4] = {P.fatt, P.facc, P.xatt, P.xacc};
+    for (int a = 0; a < 4; ++a) {
+        HIPCHK(hipMemcpy(p, arrs[a], sizeof(int64_t) * R, hipMemcpyDeviceToHost));
+        p += sizeof(int64_t) * R;
+    }
+    *len = need;
+    return PT_OK;
+}
+
+pt_status pt_load(pt_ctx **out, const void *buf, size_t len, const pt_options *opt)
+{
+    if (!out || !buf) return fail(PT_EINVAL, "null argument");
+    *out = nullptr;
+    SaveHeader hd;
+    if (len < sizeof hd) return fail(PT_EINVAL, "buffer too short");
+    std::memcpy(&hd, buf, sizeof hd);
+    if (hd.magic != kMagic || hd.version != kVersion) return fail(PT_EINVAL, "not a checkpoint of this library");
+    const int R = hd.R, L = hd.L;
+    const size_t need = sizeof hd + sizeof(double) * R + static_cast<size_t>(R) * L + sizeof(int32_t) * R +
+                        sizeof(double) * 6 * R + sizeof(int64_t) * 4 * R;
+    if (len < need) return fail(PT_EINVAL, "buffer too short");
+    const unsigned char *p = static_cast<const unsigned char *>(buf) + sizeof hd;
+    std::vector<double> T(R);
+    std::memcpy(T.data(), p, sizeof(double) * R); p += sizeof(double) * R;
+    pt_status st = validate(L, hd.q, hd.sigma, T.data(), R);
+    if (st != PT_OK) return st;
+    pt_options o;
+    if (opt) o = *opt; else pt_default_options(&o);
+    o.precision = hd.prec;
+    o.init = hd.init;
+    if (!opt || !opt->refresh_every) o.refresh_every = hd.refresh_every;
+    pt_ctx *c = nullptr;
+    if ((st = init_impl(&c, L, hd.q, hd.sigma, T.data(), R, hd.seed, &o, false)) != PT_OK) return st;
+    const Inst &P = c->inst;
+    std::vector<int32_t> perm(R), slot(R);
+    auto fail_free = [&](pt_status s) { pt_free(c); return s; };
+    if (hipMemcpy(P.spins, p, static_cast<size_t>(R) * L, hipMemcpyHostToDevice) != hipSuccess)
+        return fail_free(fail(PT_EDEVICE, "copy failed"));
+    p += static_cast<size_t>(R) * L;
+    std::memcpy(perm.data(), p, sizeof(int32_t) * R); p += sizeof(int32_t) * R;
+    for (int k = 0; k < R; ++k) {
+        if (perm[k] < 0 || perm[k] >= R) return fail_free(fail(PT_EINVAL, "corrupt permutation"));
+        slot[perm[k]] = k;
+    }
+    if (hipMemcpy(P.perm, perm.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(P.slot_of, slot.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(P.acc6, p, sizeof(double) * 6 * R, hipMemcpyHostToDevice) != hipSuccess)
+        return fail_free(fail(PT_EDEVICE, "copy failed"));
+    p += sizeof(double) * 6 * R;
+    int64_t *arrs[4] = {P.fatt, P.facc, P.xatt, P.xacc};
+    for (int a = 0; a < 4; ++a) {
+        if (hipMemcpy(arrs[a], p, sizeof(int64_t) * R, hipMemcpyHostToDevice) != hipSuccess)
+            return fail_free(fail(PT_EDEVICE, "copy failed"));
+        p += sizeof(int64_t) * R;
+    }
+    st = c->prec == PT_PREC_F32 ? launch_refresh<float>(c) : launch_refresh<double>(c);
+    if (st != PT_OK) return fail_free(st);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail_free(fail(PT_EDEVICE, "refresh failed"));
+    c->sweeps = hd.sweeps;
+    c->xsteps = hd.xsteps;
+    c->samples = hd.samples;
+    *out = c;
+    return PT_OK;
+}
+
+pt_status pt_free(pt_ctx *c)
+{
+    if (!c) return fail(PT_EINVAL, "null context");
+    (void)hipStreamSynchronize(c->stream);
+    if (c->own_ws && c->ws) (void)hipFree(c->ws);
+    delete c;
+    return PT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,100 @@
+// state.hpp -- device-resident state of one parallel-tempering instance and
+// its layout in HBM.  All arrays live in one workspace carved by `Layout`.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace ptmi {
+
+// Global counters (uint64) in Inst::ctr.
+enum Counter : int {
+    kCtrRecheck = 0,     // FP64 direct rechecks of near-threshold attempts
+    kCtrBandedMet = 1,   // Metropolis decisions inside the band
+    kCtrBandedEx = 2,    // exchange decisions inside the band
+    kCtrExactE = 3,      // exact energies computed for uncertain exchanges
+    kCtrRefresh = 4,     // field recomputations
+    kCtrEvents = 5,      // events logged (may exceed capacity)
+    kCtrError = 6,       // error bits (kErr*)
+    kCtrBarCount = 8,    // grid barrier arrivals (uint32 in the low word)
+    kCtrBarGen = 9,      // grid barrier generation
+    kCtrN = 16
+};
+enum : unsigned long long { kErrBarrierTimeout = 1ull, kErrBadLaunch = 2ull };
+
+struct Event {
+    int64_t a, b, c;
+    int32_t kind, decision;
+    double x;
+};
+
+// One instance (job): R walkers on a ring of L sites with q states.
+// Walker-indexed arrays: spins, h, E, Eerr, nupd, counts, Mw.
+// Slot-indexed arrays: beta, perm, acc6, fatt, facc; pair-indexed: xatt, xacc.
+struct Inst {
+    int32_t L, q, R, walker0;  // walker0: global id offset of walker 0 (batched jobs)
+    uint32_t key0, key1;
+    int32_t refresh_every;     // 0 = never on schedule
+    int32_t ser_cap;           // series rows kept
+    int64_t nupd_max;          // forced refresh when the drift counter exceeds this
+    double bound_init;         // bound on |h_table - h_exact| right after a refresh
+    double bound_unit;         // added to that bound by each applied flip
+    const double *J64;         // [L]
+    const float *J32;          // [L]
+    uint8_t *spins;            // [R][L], states 0..q-1
+    void *h;                   // [R][q][L] field table backing store (float or double)
+    double *E, *Eerr;          // [R] tracked energy and a rigorous bound on its error
+    int64_t *nupd;             // [R] flips applied to the table since its last refresh
+    int32_t *counts;           // [R][kQMax] number of sites per state
+    double *Mw;                // [R] magnetisation
+    int32_t *perm, *slot_of;   // [R] slot -> walker, walker -> slot
+    const double *beta;        // [R] by slot
+    double *acc6;              // [6][R] sums of E, E^2, E^4, M, M^2, M^4 by slot
+    int64_t *fatt, *facc;      // [R] by slot
+    int64_t *xatt, *xacc;      // [R] by pair
+    double *serE, *serM;       // [ser_cap][R] by slot
+    Event *events;
+    int32_t ev_cap;
+    unsigned long long *ctr;   // [kCtrN]
+};
+
+struct Layout {
+    size_t J64, J32, spins, h, E, Eerr, nupd, counts, Mw, perm, slot_of, beta, acc6, fatt, facc,
+        xatt, xacc, serE, serM, events, ctr, total;
+
+    static size_t up(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+    Layout(int L, int q, int R, size_t fbytes, int ser_cap, int ev_cap)
+    {
+        size_t o = 0;
+        auto take = [&](size_t bytes) {
+            const size_t at = o;
+            o += up(bytes);
+            return at;
+        };
+        J64 = take(sizeof(double) * L);
+        J32 = take(sizeof(float) * L);
+        spins = take(static_cast<size_t>(R) * L);
+        h = take(fbytes * static_cast<size_t>(R) * q * L);
+        E = take(sizeof(double) * R);
+        Eerr = take(sizeof(double) * R);
+        nupd = take(sizeof(int64_t) * R);
+        counts = take(sizeof(int32_t) * R * 16);
+        Mw = take(sizeof(double) * R);
+        perm = take(sizeof(int32_t) * R);
+        slot_of = take(sizeof(int32_t) * R);
+        beta = take(sizeof(double) * R);
+        acc6 = take(sizeof(double) * 6 * R);
+        fatt = take(sizeof(int64_t) * R);
+        facc = take(sizeof(int64_t) * R);
+        xatt = take(sizeof(int64_t) * R);
+        xacc = take(sizeof(int64_t) * R);
+        serE = take(sizeof(double) * static_cast<size_t>(ser_cap) * R);
+        serM = take(sizeof(double) * static_cast<size_t>(ser_cap) * R);
+        events = take(sizeof(Event) * static_cast<size_t>(ev_cap));
+        ctr = take(sizeof(unsigned long long) * kCtrN);
+        total = o;
+    }
+};
+
+}  // namespace ptmi
