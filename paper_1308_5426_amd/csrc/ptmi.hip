@@ -60,6 +60,7 @@ struct pt_ctx {
     Inst inst{};
     LdsPlan plan{}, plan_fused{};
     bool can_fuse = false;
+    bool h_in_lds = true;
     int64_t sweeps = 0, xsteps = 0, samples = 0;
     std::vector<double> T;
 };
@@ -78,13 +79,15 @@ int32_t align16(int32_t x) { return (x + 15) & ~15; }
 
 // LDS carve: couplings, field table, FP64 couplings (if they fit), per-state
 // site masks, spins, counts, reduction scratch, flags, exchange scratch.
-bool make_plan(int L, int q, int R, int prec, bool fused, size_t lds_max, LdsPlan *p)
+bool make_plan(int L, int q, int R, int prec, bool fused, bool h_in_lds, size_t lds_max, LdsPlan *p)
 {
     const int32_t fb = static_cast<int32_t>(field_bytes(prec));
     const int nblk = (L + kWave - 1) / kWave;
     int32_t o = 0;
     p->J = o; o = align16(o + fb * L);
-    p->h = o; o = align16(o + fb * q * L);
+    p->h_in_lds = h_in_lds ? 1 : 0;
+    p->h = o;
+    if (h_in_lds) o = align16(o + fb * q * L);
     p->masks = o; o = align16(o + 8 * q * nblk);
     p->sp = o; o = align16(o + L);
     p->cnt = o; o = align16(o + 4 * kQMax);
@@ -248,7 +251,7 @@ static pt_status init_impl(pt_ctx **out, int32_t L, int32_t q, double sigma, con
     if (o.init != PT_INIT_RANDOM && o.init != PT_INIT_ORDERED) return fail(PT_EINVAL, "bad init");
     if (o.threads && (o.threads % kWave || o.threads < kWave || o.threads > 1024))
         return fail(PT_EINVAL, "threads must be a multiple of 64 in [64, 1024]");
-    if (o.placement == PT_PLACE_HBM) return fail(PT_EINVAL, "HBM field placement is not available in this build");
+    if (o.placement < PT_PLACE_AUTO || o.placement > PT_PLACE_HBM) return fail(PT_EINVAL, "bad placement");
 
     pt_ctx *c = new (std::nothrow) pt_ctx();
     if (!c) return fail(PT_ENOMEM, "host allocation failed");
@@ -269,9 +272,23 @@ static pt_status init_impl(pt_ctx **out, int32_t L, int32_t q, double sigma, con
     if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess ||
         hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess)
         return bail(fail(PT_EDEVICE, "device query failed"));
-    if (!make_plan(L, q, R, c->prec, false, static_cast<size_t>(lds_max), &c->plan))
+    // Field table in LDS when it fits (or when asked), else its rows stay in HBM.
+    const size_t lmax = static_cast<size_t>(lds_max);
+    bool in_lds = o.placement != PT_PLACE_HBM && make_plan(L, q, R, c->prec, false, true, lmax, &c->plan);
+    if (o.placement == PT_PLACE_LDS && !in_lds)
         return bail(fail(PT_EINVAL, "field table of %d x %d entries does not fit in %d B of LDS", q, L, lds_max));
-    const bool fused_fits = make_plan(L, q, R, c->prec, true, static_cast<size_t>(lds_max), &c->plan_fused);
+    if (!in_lds && !make_plan(L, q, R, c->prec, false, false, lmax, &c->plan))
+        return bail(fail(PT_EINVAL, "couplings and spins of L = %d do not fit in %d B of LDS", L, lds_max));
+    bool fused_fits = make_plan(L, q, R, c->prec, true, in_lds, lmax, &c->plan_fused);
+    if (!fused_fits && in_lds && o.placement != PT_PLACE_LDS) {
+        // keep the persistent launch possible by moving the table to HBM for it
+        fused_fits = make_plan(L, q, R, c->prec, true, false, lmax, &c->plan_fused);
+        if (fused_fits) {
+            in_lds = false;
+            make_plan(L, q, R, c->prec, false, false, lmax, &c->plan);
+        }
+    }
+    c->h_in_lds = in_lds;
 
     const Layout lay = layout_of(L, q, R, c->prec, c->ser_cap, c->ev_cap);
     if (o.workspace) {

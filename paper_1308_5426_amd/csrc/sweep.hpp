@@ -24,6 +24,7 @@ namespace ptmi {
 struct LdsPlan {
     int32_t J, h, J64, masks, sp, cnt, red, misc, xch, total;
     int32_t j64_in_lds;   // 1: FP64 couplings resident in LDS
+    int32_t h_in_lds;     // 1: field table in LDS; 0: the walker's rows stay in HBM
 };
 
 // Margin for the FP64 evaluation of beta dE + ln u beyond the table bound
@@ -45,11 +46,12 @@ struct Walker {
 };
 
 template <typename F>
-__device__ __forceinline__ Walker<F> carve(unsigned char *lds, const LdsPlan &p, const Inst &P)
+__device__ __forceinline__ Walker<F> carve(unsigned char *lds, const LdsPlan &p, const Inst &P, int w)
 {
     Walker<F> W;
     W.J = reinterpret_cast<F *>(lds + p.J);
-    W.h = reinterpret_cast<F *>(lds + p.h);
+    W.h = p.h_in_lds ? reinterpret_cast<F *>(lds + p.h)
+                     : static_cast<F *>(P.h) + static_cast<size_t>(w) * P.q * P.L;
     W.J64 = p.j64_in_lds ? reinterpret_cast<const double *>(lds + p.J64) : P.J64;
     W.sp = lds + p.sp;
     W.cnt = reinterpret_cast<int32_t *>(lds + p.cnt);
@@ -112,18 +114,20 @@ __device__ void load_walker(const Inst &P, Walker<F> &W, const LdsPlan &plan, in
         W.sp[j] = ssrc[j];
         if (J64l) J64l[j] = P.J64[j];
     }
-    for (int e = threadIdx.x; e < q * L; e += blockDim.x) W.h[e] = hsrc[e];
+    if (plan.h_in_lds)
+        for (int e = threadIdx.x; e < q * L; e += blockDim.x) W.h[e] = hsrc[e];
     if (threadIdx.x < kQMax) W.cnt[threadIdx.x] = P.counts[w * kQMax + threadIdx.x];
 }
 
 template <typename F>
-__device__ void store_walker(const Inst &P, const Walker<F> &W, int w)
+__device__ void store_walker(const Inst &P, const Walker<F> &W, const LdsPlan &plan, int w)
 {
     const int L = P.L, q = P.q;
     F *hdst = static_cast<F *>(P.h) + static_cast<size_t>(w) * q * L;
     uint8_t *sdst = P.spins + static_cast<size_t>(w) * L;
     for (int j = threadIdx.x; j < L; j += blockDim.x) sdst[j] = W.sp[j];
-    for (int e = threadIdx.x; e < q * L; e += blockDim.x) hdst[e] = W.h[e];
+    if (plan.h_in_lds)
+        for (int e = threadIdx.x; e < q * L; e += blockDim.x) hdst[e] = W.h[e];
     if (threadIdx.x < kQMax) P.counts[w * kQMax + threadIdx.x] = W.cnt[threadIdx.x];
 }
 
@@ -484,12 +488,12 @@ template <typename F>
 __global__ __launch_bounds__(1024) void k_refresh(Inst P, LdsPlan plan)
 {
     extern __shared__ __align__(16) unsigned char lds[];
-    Walker<F> W = carve<F>(lds, plan, P);
     const int w = blockIdx.x;
+    Walker<F> W = carve<F>(lds, plan, P, w);
     load_walker<F>(P, W, plan, w);
     const double E = refresh_fields<F>(P, W);
     __syncthreads();
-    store_walker<F>(P, W, w);
+    store_walker<F>(P, W, plan, w);
     if (threadIdx.x == 0) {
         P.E[w] = E;
         P.Eerr[w] = 0.0;
@@ -505,8 +509,8 @@ __global__ __launch_bounds__(1024) void k_sweep(Inst P, LdsPlan plan, int64_t n0
                                                 int64_t m0, int32_t fused)
 {
     extern __shared__ __align__(16) unsigned char lds[];
-    Walker<F> W = carve<F>(lds, plan, P);
     const int w = blockIdx.x, tid = threadIdx.x;
+    Walker<F> W = carve<F>(lds, plan, P, w);
     load_walker<F>(P, W, plan, w);
     double E = P.E[w], Eerr = P.Eerr[w];
     int64_t nupd = P.nupd[w];
@@ -545,7 +549,7 @@ __global__ __launch_bounds__(1024) void k_sweep(Inst P, LdsPlan plan, int64_t n0
         }
     }
     __syncthreads();
-    store_walker<F>(P, W, w);
+    store_walker<F>(P, W, plan, w);
     if (tid == 0) {
         P.E[w] = E;
         P.Eerr[w] = Eerr;
