@@ -1,0 +1,208 @@
+"""Benchmark: spin-flip attempts per second of parallel tempering for the 1D
+long-range q-state Potts ring on one MI355X.
+
+One step = the whole hot path on one batch of synthetic input: couplings J*
+from the Hurwitz-zeta kernel, initial spins, the O(L^2) field table, then the
+sweeps (L Metropolis attempts per replica each) with a two-stage exchange step
+after every sweep, and the observables.  The default workload is L = 1024,
+q = 3, sigma = 0.4, 64 replicas with temperatures geometric in [0.3, 3.0],
+uniform random spins from seed 1234, 10^4 sweeps.
+
+Prints one JSON line (rank 0).  `value` is attempts/s = L * R * sweeps * steps
+/ time, timed between two synchronisations with the state's workspace already
+allocated in HBM.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks and unit counts
+CUS = 256
+CLOCK_HZ = 2.4e9
+LDS_BYTES_PER_CLK_CU = 128  # ds_read/ds_write bandwidth per CU per clock
+LDS_PEAK = CUS * LDS_BYTES_PER_CLK_CU * CLOCK_HZ  # 78.6 TB/s
+HBM_PEAK = 8.0e12
+
+
+def workload(name):
+    import workloads
+
+    return {"small": workloads.small, "medium": workloads.medium, "large": workloads.large}[name]()
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1308_5426_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(obs, L, attempts, sweeps_walkers, prec):
+    """LDS bytes the method must move: per attempt s_i + two table entries;
+    per accepted flip one coupling row read and two table rows read and
+    written; per refresh one FP64 coupling read per site pair; per recheck one
+    FP64 coupling and one spin per site."""
+    fb = 4 if prec == 1 else 8
+    acc = int(obs["flip_acc"].sum())
+    return (attempts * (1 + 2 * fb) + acc * 5 * fb * L + obs["n_refresh"] * 8 * L * L
+            + obs["n_recheck"] * 9 * L), acc
+
+
+def run_gpu(inst, prec, steps, warmup, max_chunk=0):
+    import torch
+
+    import paper_1308_5426_amd as pkg
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    t_kernel = []
+    obs_last = None
+
+    def one_step(timed):
+        nonlocal obs_last
+        sim = pkg.Simulation(inst.L, inst.q, inst.sigma, inst.T, inst.seed, precision=prec, init=inst.init,
+                             max_sweeps_per_launch=max_chunk or inst.sweeps)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sim.run(inst.sweeps, 1)
+        e1.record(stream)
+        obs = sim.observables()  # synchronises
+        if timed:
+            t_kernel.append(e0.elapsed_time(e1) / 1e3)
+            obs_last = obs
+        # the workspace returns to PyTorch's cache and is reused by the next step
+        sim.close()
+
+    for _ in range(warmup):
+        one_step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one_step(True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    return elapsed, t_kernel, obs_last
+
+
+def cpu_baseline(inst, seconds=12.0, mode=0):
+    """The oracle on this host's cores, on the first sweeps of the same workload."""
+    import oracle
+
+    threads = min(16, os.cpu_count() or 1)
+    pt = oracle.PT(inst.L, inst.q, inst.sigma, inst.T, inst.seed, init=inst.init, mode=mode, threads=threads)
+    t0 = time.perf_counter()
+    pt.run(1, 1)
+    t1 = time.perf_counter() - t0
+    n = max(1, int(seconds / max(t1, 1e-6)))
+    t0 = time.perf_counter()
+    pt.run(n, 1)
+    dt = time.perf_counter() - t0
+    pt.close()
+    rate = inst.L * inst.R * n / dt
+    what = "direct O(L) energy difference" if mode == 0 else "FP64 field table"
+    return {"value": rate, "unit": "attempts/s", "cores": threads, "kind": "oracle",
+            "sample": f"sweeps 2..{n + 1} of the same workload ({inst.R} replicas x {inst.L} sites, exchange "
+                      f"after each sweep), oracle mode: {what}, {dt:.1f} s"}
+
+
+def load_traffic(sha, name):
+    p = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        d = json.load(f)
+    if d.get("source_sha") != sha:
+        return None
+    return d
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="medium", choices=["small", "medium", "large"])
+    ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--sweeps", type=int, default=0, help="override the workload's sweep count")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(walkers would shard across GPUs with an all-gather of R energies per exchange step)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    inst = workload(args.workload)
+    if args.sweeps:
+        inst.sweeps = args.sweeps
+    prec = 1 if args.precision == "f32" else 0
+    elapsed, tk, obs = run_gpu(inst, prec, args.steps, args.warmup)
+    attempts = inst.L * inst.R * inst.sweeps
+    value = attempts * args.steps / elapsed
+    kern = sum(tk) / len(tk)
+    bytes_, acc = algorithmic_bytes(obs, inst.L, attempts, inst.R * inst.sweeps, prec)
+    achieved = bytes_ / kern
+    sha = kernel_source_sha()
+    tr = load_traffic(sha, f"pmc_k_sweep_{args.workload}_{args.precision}.json")
+    traffic = None if tr is None else tr["hbm_bytes_per_launch"]
+    occupied = min(CUS, inst.R)
+    out = {
+        "metric": "spin-flip attempts/sec (all replicas)",
+        "value": value,
+        "unit": "attempts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"L={inst.L} q={inst.q} sigma={inst.sigma} R={inst.R} T geometric "
+                        f"[{inst.T[0]:g},{inst.T[-1]:g}] sweeps={inst.sweeps} exchange every sweep "
+                        f"{'ordered' if inst.init else 'uniform random'} spins seed={inst.seed}",
+            "L": inst.L, "q": inst.q, "sigma": inst.sigma, "replicas": inst.R, "sweeps": inst.sweeps,
+            "field_table": "fp32 + fp64 recheck" if prec else "fp64",
+        },
+        "roofline": {
+            "bound": "lds",
+            "kernel": "k_sweep (persistent, exchange fused)",
+            "achieved": achieved / 1e9,
+            "peak": LDS_PEAK / 1e9,
+            "unit": "GB/s",
+            "frac": achieved / LDS_PEAK,
+            "frac_occupied_cus": achieved / (LDS_PEAK * occupied / CUS),
+            "traffic": traffic,
+            "kernel_ms": kern * 1e3,
+            "algorithmic_bytes_per_launch": bytes_,
+            "accepted_flips_per_launch": acc,
+            "acceptance": acc / attempts,
+            "rechecks_per_launch": obs["n_recheck"],
+            "refreshes_per_launch": obs["n_refresh"],
+            "exact_energies_per_launch": obs["n_exact_energy"],
+            "source_sha": sha,
+        },
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds, mode=0)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -68,7 +68,7 @@ typedef struct {
                                with FP64 recheck of near-threshold attempts */
     int32_t init;           /* PT_INIT_RANDOM or PT_INIT_ORDERED (all spins 1) */
     int32_t placement;      /* where the field table lives during a sweep */
-    int32_t threads;        /* threads per walker workgroup (multiple of 64, <= 1024); 0 = auto */
+    int32_t threads;        /* threads per walker workgroup (multiple of 64, <= 256); 0 = auto */
     int32_t refresh_every;  /* sweeps between O(L^2) recomputations of the fields; 0 = auto */
     int32_t series_capacity;/* sweeps of per-slot E and M to keep (0 = none) */
     int32_t event_capacity; /* entries of the banded-event log (0 = 4096) */
@@ -118,7 +118,7 @@ pt_status pt_workspace_size(int32_t L, int32_t q, int32_t R, const pt_options *o
 
 /* Creates a run: computes J*(r) on the GPU (eq. 6, FP64), draws the initial
  * spins, builds the field table and the energies, sets perm = identity.
- *   L >= 2; 2 <= q <= PT_QMAX; sigma > 0 (zeta(1+sigma) diverges at 0);
+ *   2 <= L <= 65535; 2 <= q <= PT_QMAX; sigma > 0 (zeta(1+sigma) diverges at 0);
  *   T[R] > 0, finite, ascending (slot k has temperature T[k]); R >= 1.
  * On success *out owns the device state; the work is queued on the stream. */
 pt_status pt_init(pt_ctx **out, int32_t L, int32_t q, double sigma, const double *T, int32_t R,

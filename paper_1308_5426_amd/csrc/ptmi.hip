@@ -71,15 +71,14 @@ size_t field_bytes(int prec) { return prec == PT_PREC_F32 ? sizeof(float) : size
 
 int auto_threads(int L)
 {
-    const int waves = std::min(16, std::max(1, (L + 255) / 256));
+    const int waves = std::min(kMaxSweepThreads / kWave, std::max(1, (L + 255) / 256));
     return waves * kWave;
 }
 
 int32_t align16(int32_t x) { return (x + 15) & ~15; }
 
-// LDS carve: couplings, field table, FP64 couplings (if they fit), per-state
-// site masks, spins, counts, reduction scratch, flags, exchange scratch.
-bool make_plan(int L, int q, int R, int prec, bool fused, bool h_in_lds, size_t lds_max, LdsPlan *p)
+bool make_plan_chunk(int L, int q, int R, int prec, bool fused, bool h_in_lds, size_t lds_max, int chunk,
+                     LdsPlan *p)
 {
     const int32_t fb = static_cast<int32_t>(field_bytes(prec));
     const int nblk = (L + kWave - 1) / kWave;
@@ -93,6 +92,11 @@ bool make_plan(int L, int q, int R, int prec, bool fused, bool h_in_lds, size_t 
     p->cnt = o; o = align16(o + 4 * kQMax);
     p->red = o; o = align16(o + 8 * 32);
     p->misc = o; o = align16(o + 4 * 8);
+    p->chunk = chunk;
+    p->draw = o; o = align16(o + 4 * p->chunk);
+    p->dlnu = o; o = align16(o + 8 * p->chunk);
+    p->pend = o; o = align16(o + 4 * kWave);
+    p->cs = o; o = align16(o + static_cast<int32_t>(sizeof(ChainState)));
     p->xch = o;
     if (fused) o = align16(o + 40 * R);
     if (prec == PT_PREC_F64) {
@@ -110,6 +114,19 @@ bool make_plan(int L, int q, int R, int prec, bool fused, bool h_in_lds, size_t 
     return static_cast<size_t>(o) <= lds_max;
 }
 
+// LDS carve: couplings, field table, FP64 couplings (if they fit), per-state
+// site masks, spins, counts, reduction scratch, flags, staged draws (the
+// largest chunk of 64..1024 attempts that fits), pending flips, exchange
+// scratch.
+bool make_plan(int L, int q, int R, int prec, bool fused, bool h_in_lds, size_t lds_max, LdsPlan *p)
+{
+    const int lmax = std::min(1024, ((L + kWave - 1) / kWave) * kWave);
+    if (make_plan_chunk(L, q, R, prec, fused, h_in_lds, lds_max, lmax, p)) return true;
+    for (int chunk = 512; chunk >= kWave; chunk /= 2)
+        if (chunk < lmax && make_plan_chunk(L, q, R, prec, fused, h_in_lds, lds_max, chunk, p)) return true;
+    return false;
+}
+
 Layout layout_of(int L, int q, int R, int prec, int ser_cap, int ev_cap)
 {
     return Layout(L, q, R, field_bytes(prec), ser_cap, ev_cap);
@@ -117,7 +134,7 @@ Layout layout_of(int L, int q, int R, int prec, int ser_cap, int ev_cap)
 
 pt_status validate(int32_t L, int32_t q, double sigma, const double *T, int32_t R)
 {
-    if (L < 2) return fail(PT_EINVAL, "L must be >= 2 (got %d)", L);
+    if (L < 2 || L > 65535) return fail(PT_EINVAL, "L must be in [2, 65535] (got %d)", L);
     if (q < 2 || q > PT_QMAX) return fail(PT_EINVAL, "q must be in [2, %d] (got %d)", PT_QMAX, q);
     if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(PT_EINVAL, "sigma must be finite and > 0");
     if (R < 1) return fail(PT_EINVAL, "R must be >= 1");
@@ -129,8 +146,15 @@ pt_status validate(int32_t L, int32_t q, double sigma, const double *T, int32_t 
     return PT_OK;
 }
 
+// Kernel variant by the number of states: per-lane field registers for up to
+// 4, 8 or 16 states.
 template <typename F>
-const void *sweep_fn() { return reinterpret_cast<const void *>(&k_sweep<F>); }
+const void *sweep_fn(int q)
+{
+    if (q <= 4) return reinterpret_cast<const void *>(&k_sweep<F, 4>);
+    if (q <= 8) return reinterpret_cast<const void *>(&k_sweep<F, 8>);
+    return reinterpret_cast<const void *>(&k_sweep<F, 16>);
+}
 template <typename F>
 const void *refresh_fn() { return reinterpret_cast<const void *>(&k_refresh<F>); }
 
@@ -151,17 +175,14 @@ pt_status launch_refresh(pt_ctx *c)
 template <typename F>
 pt_status launch_sweep(pt_ctx *c, int64_t n0, int32_t nsw, int32_t xevery, int64_t m0, bool fused)
 {
-    if (fused) {
-        Inst P = c->inst;
-        LdsPlan plan = c->plan_fused;
-        int32_t fu = 1;
-        void *args[] = {&P, &plan, &n0, &nsw, &xevery, &m0, &fu};
-        HIPCHK(hipLaunchCooperativeKernel(sweep_fn<F>(), dim3(c->R), dim3(c->NT), args, plan.total, c->stream));
-    } else {
-        hipLaunchKernelGGL(k_sweep<F>, dim3(c->R), dim3(c->NT), c->plan.total, c->stream, c->inst, c->plan, n0,
-                           nsw, xevery, m0, 0);
-        HIPCHK(hipGetLastError());
-    }
+    Inst P = c->inst;
+    LdsPlan plan = fused ? c->plan_fused : c->plan;
+    int32_t fu = fused ? 1 : 0;
+    void *args[] = {&P, &plan, &n0, &nsw, &xevery, &m0, &fu};
+    if (fused)
+        HIPCHK(hipLaunchCooperativeKernel(sweep_fn<F>(c->q), dim3(c->R), dim3(c->NT), args, plan.total, c->stream));
+    else
+        HIPCHK(hipLaunchKernel(sweep_fn<F>(c->q), dim3(c->R), dim3(c->NT), args, plan.total, c->stream));
     return PT_OK;
 }
 
@@ -249,8 +270,8 @@ static pt_status init_impl(pt_ctx **out, int32_t L, int32_t q, double sigma, con
     const pt_options &o = opt ? *opt : d;
     if (o.precision != PT_PREC_F64 && o.precision != PT_PREC_F32) return fail(PT_EINVAL, "bad precision");
     if (o.init != PT_INIT_RANDOM && o.init != PT_INIT_ORDERED) return fail(PT_EINVAL, "bad init");
-    if (o.threads && (o.threads % kWave || o.threads < kWave || o.threads > 1024))
-        return fail(PT_EINVAL, "threads must be a multiple of 64 in [64, 1024]");
+    if (o.threads && (o.threads % kWave || o.threads < kWave || o.threads > kMaxSweepThreads))
+        return fail(PT_EINVAL, "threads must be a multiple of 64 in [64, %d]", kMaxSweepThreads);
     if (o.placement < PT_PLACE_AUTO || o.placement > PT_PLACE_HBM) return fail(PT_EINVAL, "bad placement");
 
     pt_ctx *c = new (std::nothrow) pt_ctx();
@@ -346,7 +367,7 @@ static pt_status init_impl(pt_ctx **out, int32_t L, int32_t q, double sigma, con
         hipMemcpyAsync(P.slot_of, ident.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice, c->stream) != hipSuccess)
         return bail(fail(PT_EDEVICE, "copy of ladder failed"));
 
-    const void *sf = c->prec == PT_PREC_F32 ? sweep_fn<float>() : sweep_fn<double>();
+    const void *sf = c->prec == PT_PREC_F32 ? sweep_fn<float>(q) : sweep_fn<double>(q);
     const void *rf = c->prec == PT_PREC_F32 ? refresh_fn<float>() : refresh_fn<double>();
     const int lds_need = std::max(c->plan.total, fused_fits ? c->plan_fused.total : 0);
     if (set_lds_attr(sf, lds_need) != PT_OK || set_lds_attr(rf, c->plan.total) != PT_OK) return bail(PT_EDEVICE);

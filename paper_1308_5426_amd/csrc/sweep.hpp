@@ -8,12 +8,18 @@
 //                  exchange step (eq. 9) run by the last workgroup to arrive
 //   k_exchange     the two-stage exchange step (section 4.2) as its own launch
 //
-// One workgroup owns one walker (replica).  Every wave of the workgroup
-// evaluates the same window of 64 consecutive attempts (lane = attempt), so
-// all waves take identical decisions without communicating; the first lane
-// that is accepted (or needs an FP64 recheck) is applied, the earlier lanes
-// were rejections and changed nothing, and the window continues after it.
-// This "lookahead" keeps the sequential semantics of the Markov chain exact.
+// One workgroup owns one walker (replica).  The attempts of a sweep are taken
+// in windows of 64 consecutive attempts, lane = attempt.  Wave 0 runs the
+// Markov chain through the window: every lane holds the local fields of its
+// site for all q states in registers; the first lane that is accepted (or
+// needs an FP64 recheck) is applied, every earlier lane was a rejection and
+// changed nothing, and the later lanes correct their fields by the coupling
+// to the flipped site.  This keeps the sequential semantics of the chain
+// exactly while each accepted flip costs one LDS gather instead of an O(L)
+// table update.  At the end of the window the whole workgroup applies the
+// window's flips to the LDS table in one pass (each thread owns a set of
+// sites and applies the flips in order, so no barrier is needed between
+// them).
 #pragma once
 #include "device_common.hpp"
 #include "state.hpp"
@@ -22,14 +28,26 @@ namespace ptmi {
 
 // LDS carve (byte offsets), computed on the host by lds_plan().
 struct LdsPlan {
-    int32_t J, h, J64, masks, sp, cnt, red, misc, xch, total;
+    int32_t J, h, J64, masks, sp, cnt, red, misc, xch, draw, dlnu, pend, cs, total;
     int32_t j64_in_lds;   // 1: FP64 couplings resident in LDS
     int32_t h_in_lds;     // 1: field table in LDS; 0: the walker's rows stay in HBM
+    int32_t chunk;        // attempts whose draws are staged in LDS at a time (multiple of 64)
+};
+
+// Scalars of the walker's chain, kept by wave 0 and published through LDS.
+struct ChainState {
+    double E, Eerr;
+    int64_t nupd, nacc;
+    int32_t np[2];
+    int32_t pad[2];
 };
 
 // Margin for the FP64 evaluation of beta dE + ln u beyond the table bound
 // (FP64 rounding of the products and of the library logarithm).
 constexpr double kEvalMargin = 1e-12;
+// Workgroup size limit of the walker kernels: one wave per SIMD, so every wave
+// may use the whole register file (per-lane fields of up to 16 states).
+constexpr int kMaxSweepThreads = 256;
 // Grid barrier time-out, in wall-clock ticks (100 MHz on gfx9): 20 s.
 constexpr uint64_t kBarrierTicks = 2000000000ull;
 
@@ -43,6 +61,11 @@ struct Walker {
     uint64_t *masks;    // [q][ceil(L/64)] sites per state, for the refresh
     double *red;        // [16] reduction scratch
     int32_t *misc;      // [8]
+    uint32_t *draw;     // [chunk] site | offset << 16
+    double *dlnu;       // [chunk] ln u
+    uint32_t *pend;     // [64] flips accepted in the current window: i | a << 16 | b << 24
+    ChainState *cs;
+    int32_t chunk;
 };
 
 template <typename F>
@@ -58,6 +81,11 @@ __device__ __forceinline__ Walker<F> carve(unsigned char *lds, const LdsPlan &p,
     W.masks = reinterpret_cast<uint64_t *>(lds + p.masks);
     W.red = reinterpret_cast<double *>(lds + p.red);
     W.misc = reinterpret_cast<int32_t *>(lds + p.misc);
+    W.draw = reinterpret_cast<uint32_t *>(lds + p.draw);
+    W.dlnu = reinterpret_cast<double *>(lds + p.dlnu);
+    W.pend = reinterpret_cast<uint32_t *>(lds + p.pend);
+    W.cs = reinterpret_cast<ChainState *>(lds + p.cs);
+    W.chunk = p.chunk;
     return W;
 }
 
@@ -187,22 +215,6 @@ __device__ double refresh_fields(const Inst &P, Walker<F> &W)
         }
     }
     return -0.5 * block_sum(epart, W.red);
-}
-
-// dE = sum_{j != i} J*(|i-j|) [delta(a, s_j) - delta(b, s_j)] in FP64 (the
-// plain definition), reduced over the workgroup in a fixed order.
-template <typename F>
-__device__ double direct_dE(const Walker<F> &W, int L, int i, int a, int b)
-{
-    double part = 0.0;
-    for (int j = threadIdx.x; j < L; j += blockDim.x) {
-        const int s = W.sp[j];
-        int d = j - i;
-        d += d < 0 ? L : 0;
-        const double jv = W.J64[d];
-        part += s == a ? jv : (s == b ? -jv : 0.0);
-    }
-    return block_sum(part, W.red);
 }
 
 // Exact energy of walker w from its spins in HBM: E = -1/2 sum_j sum_{i != j}
@@ -338,7 +350,7 @@ __device__ bool grid_arrive(const Inst &P, int32_t *flag)
         __threadfence();
         const unsigned g = __hip_atomic_load(bar_gen(P), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
         const unsigned old = __hip_atomic_fetch_add(bar_count(P), 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        flag[0] = old == gridDim.x - 1;
+        flag[0] = old == static_cast<unsigned>(P.R) - 1u;
         flag[1] = static_cast<int32_t>(g);
         if (flag[0]) __threadfence();
     }
@@ -384,77 +396,270 @@ __device__ bool grid_wait(const Inst &P, int32_t *flag)
 }
 
 // ---------------------------------------------------------------------------
-// One sweep of L attempts of walker w at sweep index n (counter (t, n, w, 0)).
+// Lane broadcasts from a wave-uniform lane index (v_readlane, no LDS trip).
 // ---------------------------------------------------------------------------
-template <typename F>
-__device__ void metropolis_sweep(const Inst &P, Walker<F> &W, int w, int64_t n, double beta, double &E,
-                                 double &Eerr, int64_t &nupd, int64_t &nacc)
+__device__ __forceinline__ int rl_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ double rl_d(double v, int l)
 {
-    const int L = P.L, q = P.q, tid = threadIdx.x, NT = blockDim.x, lane = tid & (kWave - 1);
-    for (int t0 = 0; t0 < L; t0 += kWave) {
-        const int ta = t0 + lane;
-        const uint4 o = philox10(make_uint4(static_cast<uint32_t>(ta), static_cast<uint32_t>(n),
-                                            static_cast<uint32_t>(w), 0u),
-                                 P.key0, P.key1);
-        const int i = static_cast<int>(__umulhi(o.x, static_cast<uint32_t>(L)));
-        const int kk = 1 + static_cast<int>(__umulhi(o.y, static_cast<uint32_t>(q - 1)));
-        const double lnu = log(open_unit(o.z, o.w));
-        uint64_t live = __ballot(ta < L);
-        while (live) {
-            const int a = W.sp[i];
-            int b = a + kk;
-            b -= b >= q ? q : 0;
-            const double dE = static_cast<double>(W.h[a * L + i]) - static_cast<double>(W.h[b * L + i]);
-            const double x = beta * dE + lnu;
-            const double Bd = 2.0 * (P.bound_init + static_cast<double>(nupd) * P.bound_unit);
-            const double trig = beta * Bd + kBand + kEvalMargin;
-            const uint64_t cand = __ballot(x < trig) & live;
-            if (cand == 0) break;
-            const int f = __ffsll(static_cast<unsigned long long>(cand)) - 1;
-            const int i_f = __shfl(i, f), a_f = __shfl(a, f), b_f = __shfl(b, f);
-            const double x_f = __shfl(x, f), lnu_f = __shfl(lnu, f), dE_f = __shfl(dE, f);
-            bool accept = true;
-            double dEuse = dE_f, errinc = Bd;
-            if (!(x_f < -trig)) {
-                // |x| within the trigger band: decide with the FP64 direct sum
-                const double d64 = direct_dE(W, L, i_f, a_f, b_f);
-                const double x64 = beta * d64 + lnu_f;
-                accept = x64 < 0.0;
-                dEuse = d64;
-                errinc = 0.0;
-                if (tid == 0) {
-                    atomicAdd(&P.ctr[kCtrRecheck], 1ull);
-                    if (fabs(x64) <= kBand) {
-                        atomicAdd(&P.ctr[kCtrBandedMet], 1ull);
-                        log_event(P, 0, w, n, t0 + f, accept ? 1 : 0, x64);
-                    }
-                }
-            }
-            if (accept) {
-                __syncthreads();  // every wave has read the table for this window
-                F *ha = W.h + a_f * L;
-                F *hb = W.h + b_f * L;
-                for (int j = tid; j < L; j += NT) {
-                    int d = j - i_f;
-                    d += d < 0 ? L : 0;
-                    const F jv = W.J[d];
-                    ha[j] -= jv;
-                    hb[j] += jv;
-                }
-                if (tid == 0) {
-                    W.sp[i_f] = static_cast<uint8_t>(b_f);
-                    W.cnt[a_f] -= 1;
-                    W.cnt[b_f] += 1;
-                }
-                E += dEuse;
-                Eerr += errinc;
-                ++nupd;
-                ++nacc;
-                __syncthreads();
-            }
-            live &= f == kWave - 1 ? 0ull : (~0ull << (f + 1));
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(u)), l));
+    const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(u >> 32)), l));
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+// Draws of attempts [c0, c0 + cnt) of sweep n (counter (t, n, w, 0)), staged
+// in LDS by the whole workgroup: site, state offset, ln u (FP64).
+template <typename F>
+__device__ void gen_draws(const Inst &P, Walker<F> &W, int w, int64_t n, int c0, int cnt)
+{
+    for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+        const uint32_t t = static_cast<uint32_t>(c0 + e);
+        const uint4 o = philox10(make_uint4(t, static_cast<uint32_t>(n), static_cast<uint32_t>(w), 0u), P.key0, P.key1);
+        const uint32_t i = __umulhi(o.x, static_cast<uint32_t>(P.L));
+        const uint32_t k = 1u + __umulhi(o.y, static_cast<uint32_t>(P.q - 1));
+        W.draw[e] = i | (k << 16);
+        W.dlnu[e] = log(open_unit(o.z, o.w));
+    }
+}
+
+// FP64 energy difference of flipping site i from a to b in the current state,
+// by wave 0 alone: the plain sum over the window-start spins in LDS, plus the
+// change brought by each flip already accepted in this window (site ip went
+// from ap to bp, which changes its term by J*(|ip-i|) ([bp=a]-[bp=b]-[ap=a]+[ap=b])).
+template <typename F>
+__device__ double chain_direct_dE(const Walker<F> &W, int L, int i, int a, int b, int np)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    double part = 0.0;
+    for (int j = lane; j < L; j += kWave) {
+        const int s = W.sp[j];
+        int d = j - i;
+        d += d < 0 ? L : 0;
+        const double jv = W.J64[d];
+        part += s == a ? jv : (s == b ? -jv : 0.0);
+    }
+    double tot = rl_d(wave_sum(part), 0);
+    for (int p = 0; p < np; ++p) {
+        const uint32_t pk = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(W.pend[p])));
+        const int ip = pk & 0xFFFF, ap = (pk >> 16) & 0xFF, bp = pk >> 24;
+        const int c = (a == bp) - (b == bp) - (a == ap) + (b == ap);
+        if (c != 0) {
+            int d = ip - i;
+            d += d < 0 ? L : 0;
+            tot += static_cast<double>(c) * W.J64[d];
         }
     }
+    return tot;
+}
+
+struct ChainRegs {
+    double E, Eerr;
+    int64_t nupd, nacc;
+};
+
+// Field of state c at site i as the chain sees it: the table entry (window
+// start) plus the flips 0..np-1 already accepted in this window, applied in
+// order -- the same operations, in the same order, as the running
+// corrections and the flush, so all three agree bit for bit.
+template <typename F>
+__device__ __forceinline__ F field_now(const Walker<F> &W, int L, int c, int i, int np)
+{
+    F v = W.h[c * L + i];
+    for (int p = 0; p < np; ++p) {
+        const uint32_t pk = W.pend[p];
+        const int ip = pk & 0xFFFF, ap = (pk >> 16) & 0xFF, bp = pk >> 24;
+        if (c == ap || c == bp) {
+            int d = i - ip;
+            d += d < 0 ? L : 0;
+            v = c == ap ? v - W.J[d] : v + W.J[d];
+        }
+    }
+    return v;
+}
+
+// Wave 0: the chain through attempts [t0, t0 + 64) (lanes past `cend` idle).
+// Each lane keeps only the two fields its attempt needs, ha = h[a][i] and
+// hb = h[b][i], and corrects them after every accepted flip.
+template <typename F>
+__device__ void chain_window(const Inst &P, Walker<F> &W, int w, int64_t n, double beta, int t0, int c0, int cend,
+                             ChainRegs &cr)
+{
+    const int L = P.L, q = P.q, lane = threadIdx.x & (kWave - 1);
+    const int ta = t0 + lane;
+    const bool valid = ta < cend;
+    const uint32_t dr = valid ? W.draw[ta - c0] : 0u;
+    const int i = static_cast<int>(dr & 0xFFFFu);
+    const int kk = static_cast<int>(dr >> 16);
+    const double lnu = valid ? W.dlnu[ta - c0] : 0.0;
+    int a = W.sp[i];
+    int b = a + kk;
+    b -= b >= q ? q : 0;
+    F ha = W.h[a * L + i], hb = W.h[b * L + i];
+    uint64_t live = __ballot(valid);
+    int np = 0;
+    while (live) {
+        const double dE = static_cast<double>(ha) - static_cast<double>(hb);
+        const double Bd = 2.0 * (P.bound_init + static_cast<double>(cr.nupd) * P.bound_unit);
+        const double trig = beta * Bd + kBand + kEvalMargin;
+        const double x = beta * dE + lnu;
+        const uint64_t cand = __ballot(x < trig) & live;
+        if (cand == 0) break;
+        const int f = __builtin_ctzll(cand);
+        const int i_f = rl_i(i, f), a_f = rl_i(a, f), b_f = rl_i(b, f);
+        const double x_f = rl_d(x, f);
+        bool accept = true;
+        double dEuse = rl_d(dE, f), errinc = Bd;
+        if (!(x_f < -trig)) {
+            // |x| inside the trigger band: decide with the FP64 direct sum
+            const double d64 = chain_direct_dE(W, L, i_f, a_f, b_f, np);
+            const double x64 = beta * d64 + rl_d(lnu, f);
+            accept = x64 < 0.0;
+            dEuse = d64;
+            errinc = 0.0;
+            if (lane == 0) {
+                atomicAdd(&P.ctr[kCtrRecheck], 1ull);
+                if (fabs(x64) <= kBand) {
+                    atomicAdd(&P.ctr[kCtrBandedMet], 1ull);
+                    log_event(P, 0, w, n, t0 + f, accept ? 1 : 0, x64);
+                }
+            }
+        }
+        if (accept) {
+            if (lane == 0) {
+                W.pend[np] = static_cast<uint32_t>(i_f) | (static_cast<uint32_t>(a_f) << 16) |
+                             (static_cast<uint32_t>(b_f) << 24);
+                W.cnt[a_f] -= 1;
+                W.cnt[b_f] += 1;
+            }
+            ++np;
+            if (sizeof(F) == sizeof(double)) {  // FP32 tables take E from the flush's exact sums
+                cr.E += dEuse;
+                cr.Eerr += errinc;
+            }
+            ++cr.nupd;
+            ++cr.nacc;
+            if (i == i_f) {
+                // this lane's own site changed state: its two fields are re-derived
+                a = b_f;
+                b = a + kk;
+                b -= b >= q ? q : 0;
+                ha = field_now(W, L, a, i, np);
+                hb = field_now(W, L, b, i, np);
+            } else {
+                int d = i - i_f;
+                d += d < 0 ? L : 0;
+                const F jv = W.J[d];
+                ha = a == a_f ? ha - jv : (a == b_f ? ha + jv : ha);
+                hb = b == a_f ? hb - jv : (b == b_f ? hb + jv : hb);
+            }
+        }
+        live &= f == kWave - 1 ? 0ull : (~0ull << (f + 1));
+    }
+    if (lane == 0) W.cs->np[(t0 / kWave) & 1] = np;
+}
+
+// Whole workgroup: apply the window's np flips to the table.  Each thread
+// holds up to 4 sites x q states in registers and applies the flips in
+// order.  With an FP32 table the same pass forms the exact FP64 energy change
+// of every flip, sum_j J*(|j-i|)[delta(a, s_j) - delta(b, s_j)], over the
+// spins as they were just before it (partial sums per thread).
+template <typename F, int QT>
+__device__ void flush_window(const Inst &P, Walker<F> &W, int np, double &part)
+{
+    constexpr int NJB = 4;
+    constexpr bool kF32 = sizeof(F) == sizeof(float);
+    const int L = P.L, q = P.q, tid = threadIdx.x, NT = blockDim.x;
+    if (!kF32 && tid == 0)
+        for (int p = 0; p < np; ++p) {
+            const uint32_t pk = W.pend[p];
+            W.sp[pk & 0xFFFFu] = static_cast<uint8_t>(pk >> 24);
+        }
+    for (int jb = 0; jb < L; jb += NT * NJB) {
+        int jm[NJB];
+        bool ok[NJB];
+        F hr[QT][NJB];
+        int sr[NJB];
+#pragma unroll
+        for (int m = 0; m < NJB; ++m) {
+            const int j = jb + m * NT + tid;
+            ok[m] = j < L;
+            jm[m] = ok[m] ? j : 0;
+            sr[m] = (kF32 && ok[m]) ? W.sp[j] : -1;
+        }
+#pragma unroll
+        for (int c = 0; c < QT; ++c)
+#pragma unroll
+            for (int m = 0; m < NJB; ++m) hr[c][m] = (c < q && ok[m]) ? W.h[c * L + jm[m]] : F(0);
+        for (int p = 0; p < np; ++p) {
+            const uint32_t pk = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(W.pend[p])));
+            const int ip = pk & 0xFFFF, ap = (pk >> 16) & 0xFF, bp = pk >> 24;
+            F jv[NJB];
+            int dd[NJB];
+#pragma unroll
+            for (int m = 0; m < NJB; ++m) {
+                int d = jm[m] - ip;
+                d += d < 0 ? L : 0;
+                dd[m] = d;
+                jv[m] = W.J[d];
+            }
+#pragma unroll
+            for (int c = 0; c < QT; ++c) {
+                if (c == ap) {
+#pragma unroll
+                    for (int m = 0; m < NJB; ++m) hr[c][m] -= jv[m];
+                }
+                if (c == bp) {
+#pragma unroll
+                    for (int m = 0; m < NJB; ++m) hr[c][m] += jv[m];
+                }
+            }
+            if (kF32) {
+#pragma unroll
+                for (int m = 0; m < NJB; ++m) {
+                    const int s = sr[m];
+                    if (s == ap || s == bp) {
+                        const double j64 = W.J64[dd[m]];
+                        part += s == ap ? j64 : -j64;
+                    }
+                    sr[m] = (ok[m] && jm[m] == ip) ? bp : s;
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < QT; ++c)
+#pragma unroll
+            for (int m = 0; m < NJB; ++m)
+                if (c < q && ok[m]) W.h[c * L + jm[m]] = hr[c][m];
+        if (kF32) {
+#pragma unroll
+            for (int m = 0; m < NJB; ++m)
+                if (ok[m]) W.sp[jm[m]] = static_cast<uint8_t>(sr[m]);
+        }
+    }
+}
+
+// One sweep of walker w at sweep index n.  Returns this thread's part of the
+// exact energy change (FP32 table; zero otherwise).
+template <typename F, int QT>
+__device__ double sweep_walker(const Inst &P, Walker<F> &W, int w, int64_t n, double beta, ChainRegs &cr)
+{
+    const int L = P.L, wave = threadIdx.x / kWave;
+    double part = 0.0;
+    for (int c0 = 0; c0 < L; c0 += W.chunk) {
+        const int cend = min(L, c0 + W.chunk);
+        gen_draws<F>(P, W, w, n, c0, cend - c0);
+        __syncthreads();
+        for (int t0 = c0; t0 < cend; t0 += kWave) {
+            if (wave == 0) chain_window<F>(P, W, w, n, beta, t0, c0, cend, cr);
+            __syncthreads();
+            const int np = W.cs->np[(t0 / kWave) & 1];
+            if (np > 0) {
+                flush_window<F, QT>(P, W, np, part);
+                __syncthreads();
+            }
+        }
+    }
+    return part;
 }
 
 template <typename F>
@@ -485,7 +690,7 @@ __device__ void record_sweep(const Inst &P, const Walker<F> &W, int w, int slot,
 // Kernels
 // ---------------------------------------------------------------------------
 template <typename F>
-__global__ __launch_bounds__(1024) void k_refresh(Inst P, LdsPlan plan)
+__global__ __launch_bounds__(kMaxSweepThreads) void k_refresh(Inst P, LdsPlan plan)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     const int w = blockIdx.x;
@@ -504,57 +709,83 @@ __global__ __launch_bounds__(1024) void k_refresh(Inst P, LdsPlan plan)
     }
 }
 
-template <typename F>
-__global__ __launch_bounds__(1024) void k_sweep(Inst P, LdsPlan plan, int64_t n0, int32_t nsw, int32_t xevery,
-                                                int64_t m0, int32_t fused)
+// The life of one walker of instance P through sweeps n0 .. n0 + nsw - 1:
+// load its state into LDS, sweep, record, refresh on schedule, and (fused)
+// meet the instance's other walkers at the device barrier for the exchange.
+// Returns false if the barrier timed out.
+template <typename F, int QT>
+__device__ bool run_walker(const Inst &P, const LdsPlan &plan, unsigned char *lds, int w, int64_t n0, int32_t nsw,
+                           int32_t xevery, int64_t m0, bool fused)
 {
-    extern __shared__ __align__(16) unsigned char lds[];
-    const int w = blockIdx.x, tid = threadIdx.x;
+    const int tid = threadIdx.x;
     Walker<F> W = carve<F>(lds, plan, P, w);
     load_walker<F>(P, W, plan, w);
-    double E = P.E[w], Eerr = P.Eerr[w];
-    int64_t nupd = P.nupd[w];
+    ChainRegs cr{P.E[w], P.Eerr[w], P.nupd[w], 0};
     int64_t m = m0;
     __syncthreads();
     for (int s = 0; s < nsw; ++s) {
         const int64_t n = n0 + s;
         const int slot = __hip_atomic_load(&P.slot_of[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const double beta = P.beta[slot];
-        int64_t nacc = 0;
-        metropolis_sweep<F>(P, W, w, n, beta, E, Eerr, nupd, nacc);
+        cr.nacc = 0;
+        const double part = sweep_walker<F, QT>(P, W, w, n, beta, cr);
+        if (sizeof(F) == sizeof(float)) {
+            const double dEs = block_sum(part, W.red);  // exact FP64 energy change of the sweep
+            if (tid < kWave) cr.E += dEs;
+        }
+        if (tid == 0) {
+            W.cs->E = cr.E;
+            W.cs->Eerr = cr.Eerr;
+            W.cs->nupd = cr.nupd;
+            W.cs->nacc = cr.nacc;
+        }
         __syncthreads();
-        record_sweep<F>(P, W, w, slot, n, E, nacc);
-        if ((P.refresh_every > 0 && (n + 1) % P.refresh_every == 0) || nupd > P.nupd_max) {
-            E = refresh_fields<F>(P, W);
-            Eerr = 0.0;
-            nupd = 0;
+        cr.E = W.cs->E;
+        cr.Eerr = W.cs->Eerr;
+        cr.nupd = W.cs->nupd;
+        cr.nacc = W.cs->nacc;
+        record_sweep<F>(P, W, w, slot, n, cr.E, cr.nacc);
+        if ((P.refresh_every > 0 && (n + 1) % P.refresh_every == 0) || cr.nupd > P.nupd_max) {
+            cr.E = refresh_fields<F>(P, W);
+            cr.Eerr = 0.0;
+            cr.nupd = 0;
             if (tid == 0) atomicAdd(&P.ctr[kCtrRefresh], 1ull);
             __syncthreads();
         }
         if (fused && xevery > 0 && (s + 1) % xevery == 0) {
             for (int j = tid; j < P.L; j += blockDim.x) P.spins[static_cast<size_t>(w) * P.L + j] = W.sp[j];
             if (tid == 0) {
-                P.E[w] = E;
-                P.Eerr[w] = Eerr;
+                P.E[w] = cr.E;
+                P.Eerr[w] = cr.Eerr;
             }
             if (grid_arrive(P, W.misc)) {
                 exchange_step(P, m, carve_x(lds + plan.xch, P.R), W.red);
                 grid_release(P, W.misc);
             } else if (!grid_wait(P, W.misc)) {
-                return;  // time-out or error raised elsewhere: leave; the host reports it
+                return false;  // time-out or error raised elsewhere: leave; the host reports it
             }
-            E = __hip_atomic_load(&P.E[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            Eerr = __hip_atomic_load(&P.Eerr[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            cr.E = __hip_atomic_load(&P.E[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            cr.Eerr = __hip_atomic_load(&P.Eerr[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             ++m;
         }
     }
     __syncthreads();
     store_walker<F>(P, W, plan, w);
     if (tid == 0) {
-        P.E[w] = E;
-        P.Eerr[w] = Eerr;
-        P.nupd[w] = nupd;
+        P.E[w] = cr.E;
+        P.Eerr[w] = cr.Eerr;
+        P.nupd[w] = cr.nupd;
     }
+    __syncthreads();
+    return true;
+}
+
+template <typename F, int QT>
+__global__ __launch_bounds__(kMaxSweepThreads) void k_sweep(Inst P, LdsPlan plan, int64_t n0, int32_t nsw,
+                                                            int32_t xevery, int64_t m0, int32_t fused)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    (void)run_walker<F, QT>(P, plan, lds, blockIdx.x, n0, nsw, xevery, m0, fused != 0);
 }
 
 __global__ __launch_bounds__(1024) void k_exchange(Inst P, int64_t m)

@@ -141,7 +141,7 @@ def test_fused_equals_unfused(pkg, orc, precision):
     run_pair(pkg, orc, 96, 4, 0.6, T, 7, 60, 3, precision=precision, steps=3)
 
 
-@pytest.mark.parametrize("L,q,threads", [(100, 2, 64), (1000, 5, 256), (1000, 5, 1024), (1000, 5, 64),
+@pytest.mark.parametrize("L,q,threads", [(100, 2, 64), (1000, 5, 256), (1000, 5, 192), (1000, 5, 64),
                                          (257, 16, 128), (2, 2, 64), (3, 3, 64)])
 def test_tiles_and_ragged_sizes(pkg, orc, L, q, threads):
     T = _ladder(0.2, 3.0, 6)
