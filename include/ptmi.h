@@ -73,6 +73,7 @@ typedef struct {
     int32_t series_capacity;/* sweeps of per-slot E and M to keep (0 = none) */
     int32_t event_capacity; /* entries of the banded-event log (0 = 4096) */
     int32_t max_sweeps_per_launch; /* 0 = auto */
+    int32_t lds_budget;     /* batch/server: LDS bytes per walker workgroup (0 = auto) */
     void *stream;           /* hipStream_t to run on, NULL = the null stream */
     void *workspace;        /* optional caller-owned device memory for all state */
     size_t workspace_bytes; /* its size; must be >= pt_workspace_size() */
@@ -172,6 +173,66 @@ pt_status pt_free(pt_ctx *ctx);
 
 /* Thread-local message of the last failure on this thread ("" if none). */
 const char *pt_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Batches: many independent instances of uneven size in one persistent    */
+/* launch.  Workgroups take walkers job by job from a ticket counter, so a */
+/* job's walkers always meet at its exchange barrier; each job runs `sweeps`*/
+/* sweeps with an exchange step after every `exchange_every`-th.  Results  */
+/* per job equal those of the same job run alone (same streams).           */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t L, q;            /* as pt_init */
+    double sigma;
+    const double *T;         /* [R] ascending; copied at creation */
+    int32_t R;
+    uint64_t seed;
+    int64_t sweeps;          /* >= 0 */
+    int32_t exchange_every;  /* >= 1 */
+    int32_t init;            /* PT_INIT_RANDOM or PT_INIT_ORDERED */
+} pt_job_desc;
+
+typedef struct pt_batch pt_batch;
+
+/* Device bytes for a batch (all jobs' state plus the job table). */
+pt_status pt_batch_workspace_size(const pt_job_desc *jobs, int32_t njobs, const pt_options *opt, size_t *bytes);
+/* Validates and lays out the jobs; opt->threads and opt->lds_budget pick the
+ * walker workgroup shape (0 = auto).  Nothing runs yet. */
+pt_status pt_batch_create(pt_batch **out, const pt_job_desc *jobs, int32_t njobs, const pt_options *opt);
+/* One launch that sets up and runs every job to completion.  Asynchronous. */
+pt_status pt_batch_run(pt_batch *b);
+/* Observables and spins of job `job` after pt_batch_run (synchronising). */
+pt_status pt_batch_observables(pt_batch *b, int32_t job, pt_obs *out);
+pt_status pt_batch_get_spins(pt_batch *b, int32_t job, uint8_t *spins_out, int32_t *perm_out);
+/* Workgroups used by the launch and threads per workgroup (for reporting). */
+pt_status pt_batch_shape(pt_batch *b, int32_t *workgroups, int32_t *threads, int32_t *lds_bytes);
+pt_status pt_batch_free(pt_batch *b);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: a persistent launch that keeps taking jobs while it runs.      */
+/* Submitted jobs wait in a host queue until their state fits in the device */
+/* arena (admission by device memory), are then published to the running  */
+/* kernel, and their results are copied back when their last walker ends. */
+/* A host thread does the admission, publication and completion polling.   */
+/* ------------------------------------------------------------------------ */
+typedef struct pt_server pt_server;
+
+/* arena_bytes of device memory for job state (opt->workspace may supply it);
+ * max_jobs bounds the number of submissions over the server's life. */
+pt_status pt_server_start(pt_server **out, size_t arena_bytes, int32_t max_jobs, const pt_options *opt);
+/* Queues a job (T copied); *id_out receives its id.  Thread-safe. */
+pt_status pt_server_submit(pt_server *s, const pt_job_desc *job, int64_t *id_out);
+/* *done_out = 1 when job id has finished; then fills *out if non-NULL. */
+pt_status pt_server_poll(pt_server *s, int64_t id, int32_t *done_out, pt_obs *out);
+/* Blocks until job id has finished (or timeout_s elapses: PT_ESTATE). */
+pt_status pt_server_wait(pt_server *s, int64_t id, double timeout_s, pt_obs *out);
+/* Host times of job id (seconds on a monotonic clock): submitted, admitted
+ * (published to the device), finished (results copied back). */
+pt_status pt_server_times(pt_server *s, int64_t id, double *submitted, double *admitted, double *finished);
+/* Spins [R][L] (1..q) and perm [R] of a finished job. */
+pt_status pt_server_get_spins(pt_server *s, int64_t id, uint8_t *spins_out, int32_t *perm_out);
+/* Drains every submitted job, stops the persistent launch, frees the server. */
+pt_status pt_server_stop(pt_server *s);
 
 #ifdef __cplusplus
 }

@@ -44,6 +44,7 @@ class Options(ctypes.Structure):
         ("series_capacity", ctypes.c_int32),
         ("event_capacity", ctypes.c_int32),
         ("max_sweeps_per_launch", ctypes.c_int32),
+        ("lds_budget", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
@@ -70,10 +71,20 @@ class Obs(ctypes.Structure):
     ]
 
 
+class JobDesc(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("q", ctypes.c_int32), ("sigma", ctypes.c_double),
+                ("T", ctypes.c_void_p), ("R", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("sweeps", ctypes.c_int64), ("exchange_every", ctypes.c_int32), ("init", ctypes.c_int32)]
+
+
 EXPORTS = [
     "pt_default_options", "pt_workspace_size", "pt_init", "pt_sweep", "pt_exchange", "pt_run",
     "pt_observables", "pt_get_spins", "pt_get_jstar", "pt_get_series", "pt_get_events",
     "pt_reset_stats", "pt_synchronize", "pt_save", "pt_load", "pt_free", "pt_last_error",
+    "pt_batch_workspace_size", "pt_batch_create", "pt_batch_run", "pt_batch_observables",
+    "pt_batch_get_spins", "pt_batch_shape", "pt_batch_free",
+    "pt_server_start", "pt_server_submit", "pt_server_poll", "pt_server_wait", "pt_server_times",
+    "pt_server_get_spins", "pt_server_stop",
 ]
 
 _lib = None
@@ -109,6 +120,21 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.pt_free.argtypes = [_P]
     L.pt_last_error.restype = ctypes.c_char_p
     L.pt_last_error.argtypes = []
+    JD, OP, OB = ctypes.POINTER(JobDesc), ctypes.POINTER(Options), ctypes.POINTER(Obs)
+    L.pt_batch_workspace_size.argtypes = [JD, i32, OP, ctypes.POINTER(ctypes.c_size_t)]
+    L.pt_batch_create.argtypes = [pp, JD, i32, OP]
+    L.pt_batch_run.argtypes = [_P]
+    L.pt_batch_observables.argtypes = [_P, i32, OB]
+    L.pt_batch_get_spins.argtypes = [_P, i32, _P, _P]
+    L.pt_batch_shape.argtypes = [_P, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.pt_batch_free.argtypes = [_P]
+    L.pt_server_start.argtypes = [pp, ctypes.c_size_t, i32, OP]
+    L.pt_server_submit.argtypes = [_P, JD, ctypes.POINTER(i64)]
+    L.pt_server_poll.argtypes = [_P, i64, ctypes.POINTER(i32), OB]
+    L.pt_server_wait.argtypes = [_P, i64, d, OB]
+    L.pt_server_times.argtypes = [_P, i64, ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(d)]
+    L.pt_server_get_spins.argtypes = [_P, i64, _P, _P]
+    L.pt_server_stop.argtypes = [_P]
     for name in EXPORTS:
         if name != "pt_default_options" and name != "pt_last_error":
             getattr(L, name).restype = ctypes.c_int
@@ -124,6 +150,36 @@ def _check(status):
 
 def _ptr(a):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _obs_buffers(R):
+    arrs = {k: np.zeros(R) for k in ("E", "M", "sumE", "sumE2", "sumE4", "sumM", "sumM2", "sumM4")}
+    ints = {k: np.zeros(R, np.int64) for k in ("flip_att", "flip_acc")}
+    pairs = {k: np.zeros(max(R - 1, 1), np.int64) for k in ("xchg_att", "xchg_acc")}
+    perm = np.zeros(R, np.int32)
+    o = Obs()
+    for k, v in {**arrs, **ints, **pairs}.items():
+        setattr(o, k, _ptr(v))
+    o.perm = _ptr(perm)
+    return o, arrs, ints, pairs, perm
+
+
+def _obs_dict(o, arrs, ints, pairs, perm, R):
+    out = {**arrs, **ints}
+    out.update({k: v[: R - 1] for k, v in pairs.items()})
+    out.update(perm=perm, sweeps=o.sweeps, exchange_steps=o.exchange_steps, samples=o.samples,
+               n_recheck=o.n_recheck, n_banded=o.n_banded, n_exact_energy=o.n_exact_energy,
+               n_refresh=o.n_refresh, n_events_dropped=o.n_events_dropped)
+    return out
+
+
+def _job_desc(job, keep):
+    """job: dict or object with L, q, sigma, T, seed, sweeps[, exchange_every, init]."""
+    g = (lambda k, d=None: job.get(k, d)) if isinstance(job, dict) else (lambda k, d=None: getattr(job, k, d))
+    T = np.ascontiguousarray(np.asarray(g("T"), dtype=np.float64))
+    keep.append(T)
+    return JobDesc(int(g("L")), int(g("q")), float(g("sigma")), T.ctypes.data, len(T), int(g("seed")),
+                   int(g("sweeps")), int(g("exchange_every", 1) or 1), int(g("init", 0) or 0))
 
 
 def _torch_device_memory(nbytes):
@@ -288,3 +344,120 @@ class Simulation:
         Simulation.__init__(self, L, q, sigma, T, seed, _ctx=ctx, _ws=ws,
                             series_capacity=opt.series_capacity)
         return self
+
+
+class Batch:
+    """Many independent runs of uneven size in one persistent launch (pt_batch).
+
+    jobs: list of dicts/objects with L, q, sigma, T, seed, sweeps, and optional
+    exchange_every (default 1) and init.  threads / lds_budget set the walker
+    workgroup shape (0 = library default)."""
+
+    def __init__(self, jobs, precision=PREC_F64, threads=0, lds_budget=0):
+        self._lib = load_library()
+        keep = []
+        self.jobs = list(jobs)
+        arr = (JobDesc * len(self.jobs))(*[_job_desc(j, keep) for j in self.jobs])
+        opt = Options()
+        self._lib.pt_default_options(ctypes.byref(opt))
+        opt.precision, opt.threads, opt.lds_budget = int(precision), int(threads), int(lds_budget)
+        nbytes = ctypes.c_size_t(0)
+        _check(self._lib.pt_batch_workspace_size(arr, len(self.jobs), ctypes.byref(opt), ctypes.byref(nbytes)))
+        self._ws, stream = _torch_device_memory(nbytes.value)
+        opt.stream, opt.workspace, opt.workspace_bytes = stream, self._ws.data_ptr(), self._ws.numel()
+        h = ctypes.c_void_p()
+        _check(self._lib.pt_batch_create(ctypes.byref(h), arr, len(self.jobs), ctypes.byref(opt)))
+        self._h = h
+        self.R = [len(np.asarray(k["T"] if isinstance(k, dict) else k.T)) for k in self.jobs]
+
+    def run(self):
+        _check(self._lib.pt_batch_run(self._h))
+
+    def shape(self):
+        w, t, l = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(self._lib.pt_batch_shape(self._h, ctypes.byref(w), ctypes.byref(t), ctypes.byref(l)))
+        return dict(workgroups=w.value, threads=t.value, lds_bytes=l.value)
+
+    def observables(self, j) -> dict:
+        R = self.R[j]
+        o, arrs, ints, pairs, perm = _obs_buffers(R)
+        _check(self._lib.pt_batch_observables(self._h, int(j), ctypes.byref(o)))
+        return _obs_dict(o, arrs, ints, pairs, perm, R)
+
+    def spins(self, j):
+        R = self.R[j]
+        L = int(self.jobs[j]["L"] if isinstance(self.jobs[j], dict) else self.jobs[j].L)
+        s = np.zeros((R, L), np.uint8)
+        p = np.zeros(R, np.int32)
+        _check(self._lib.pt_batch_get_spins(self._h, int(j), _ptr(s), _ptr(p)))
+        return s, p
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.pt_batch_free(self._h)
+            self._h = None
+            self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous batching: a persistent launch that takes jobs while it runs
+    (pt_server).  Jobs wait until their state fits in the device arena."""
+
+    def __init__(self, arena_bytes=1 << 30, max_jobs=8192, precision=PREC_F64, threads=0, lds_budget=0):
+        self._lib = load_library()
+        opt = Options()
+        self._lib.pt_default_options(ctypes.byref(opt))
+        opt.precision, opt.threads, opt.lds_budget = int(precision), int(threads), int(lds_budget)
+        h = ctypes.c_void_p()
+        _check(self._lib.pt_server_start(ctypes.byref(h), int(arena_bytes), int(max_jobs), ctypes.byref(opt)))
+        self._h = h
+        self._R, self._L = {}, {}
+
+    def submit(self, job) -> int:
+        keep = []
+        d = _job_desc(job, keep)
+        jid = ctypes.c_int64()
+        _check(self._lib.pt_server_submit(self._h, ctypes.byref(d), ctypes.byref(jid)))
+        self._R[jid.value], self._L[jid.value] = d.R, d.L
+        return jid.value
+
+    def poll(self, jid):
+        R = self._R[jid]
+        o, arrs, ints, pairs, perm = _obs_buffers(R)
+        done = ctypes.c_int32()
+        _check(self._lib.pt_server_poll(self._h, int(jid), ctypes.byref(done), ctypes.byref(o)))
+        return _obs_dict(o, arrs, ints, pairs, perm, R) if done.value else None
+
+    def wait(self, jid, timeout=600.0) -> dict:
+        R = self._R[jid]
+        o, arrs, ints, pairs, perm = _obs_buffers(R)
+        _check(self._lib.pt_server_wait(self._h, int(jid), float(timeout), ctypes.byref(o)))
+        return _obs_dict(o, arrs, ints, pairs, perm, R)
+
+    def times(self, jid):
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(self._lib.pt_server_times(self._h, int(jid), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def spins(self, jid):
+        s = np.zeros((self._R[jid], self._L[jid]), np.uint8)
+        p = np.zeros(self._R[jid], np.int32)
+        _check(self._lib.pt_server_get_spins(self._h, int(jid), _ptr(s), _ptr(p)))
+        return s, p
+
+    def stop(self):
+        if getattr(self, "_h", None):
+            h, self._h = self._h, None
+            _check(self._lib.pt_server_stop(h))
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass

@@ -99,10 +99,8 @@ __device__ double hurwitz_zeta(double s, double a)
 
 // J*(r) for 1 <= r <= L/2 by eq. 6, mirrored to L - r (J*(r) = J*(L-r));
 // J*(0) = 0 (the self term i = j is excluded from eq. 2).
-__global__ void k_jstar(int32_t L, double sigma, double *__restrict__ J64, float *__restrict__ J32)
+__device__ __forceinline__ void jstar_entry(int32_t L, double sigma, int r, double *J64, float *J32)
 {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r > L / 2) return;
     double v = 0.0;
     if (r > 0) {
         const double s = 1.0 + sigma;
@@ -116,6 +114,12 @@ __global__ void k_jstar(int32_t L, double sigma, double *__restrict__ J64, float
         J64[L - r] = v;
         J32[L - r] = static_cast<float>(v);
     }
+}
+
+__global__ void k_jstar(int32_t L, double sigma, double *__restrict__ J64, float *__restrict__ J32)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r <= L / 2) jstar_entry(L, sigma, r, J64, J32);
 }
 
 }  // namespace ptmi

@@ -1,0 +1,656 @@
+// host_jobs.hpp -- host side of batches and of the server: job layout in one
+// arena, the job table, the persistent launch of k_jobs, and (server) a host
+// thread that admits queued jobs by device memory, publishes them to the
+// running kernel and collects finished jobs.  Included once, by ptmi.hip.
+#pragma once
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+
+namespace {
+
+constexpr int kJobEvents = 64;
+
+double now_s()
+{
+    using clk = std::chrono::steady_clock;
+    return std::chrono::duration<double>(clk::now().time_since_epoch()).count();
+}
+
+pt_status validate_job(const pt_job_desc &j)
+{
+    pt_status st = validate(j.L, j.q, j.sigma, j.T, j.R);
+    if (st != PT_OK) return st;
+    if (j.sweeps < 0 || j.sweeps > INT32_MAX) return fail(PT_EINVAL, "sweeps must be in [0, 2^31)");
+    if (j.exchange_every < 1) return fail(PT_EINVAL, "exchange_every must be >= 1");
+    if (j.init != PT_INIT_RANDOM && j.init != PT_INIT_ORDERED) return fail(PT_EINVAL, "bad init");
+    return PT_OK;
+}
+
+size_t job_bytes(const pt_job_desc &j, int prec)
+{
+    return Layout::up(layout_of(j.L, j.q, j.R, prec, 0, kJobEvents).total);
+}
+
+// Carve of one job inside a workgroup LDS budget: table in LDS if it fits,
+// else in HBM; which kernel variant runs it.
+pt_status job_plan(const pt_job_desc &j, int prec, int budget, LdsPlan *plan, int32_t *variant)
+{
+    const size_t b = static_cast<size_t>(budget);
+    bool in_lds = make_plan(j.L, j.q, j.R, prec, true, true, b, plan);
+    if (!in_lds && !make_plan(j.L, j.q, j.R, prec, true, false, b, plan))
+        return fail(PT_EINVAL, "job with L = %d, R = %d does not fit an LDS budget of %d B", j.L, j.R, budget);
+    int32_t v = 0;
+    if (plan->h_in_lds) v |= kVarHLds;
+    if (plan->j64_in_lds) v |= kVarJ64Lds;
+    if (j.q <= 4) v |= kVarRegFlush;
+    *variant = v;
+    return PT_OK;
+}
+
+template <typename F>
+const void *jobs_fn() { return reinterpret_cast<const void *>(&k_jobs<F>); }
+
+const void *jobs_fn_prec(int prec) { return prec == PT_PREC_F32 ? jobs_fn<float>() : jobs_fn<double>(); }
+
+// Resident workgroups of k_jobs for (threads, budget) on this device.
+pt_status jobs_capacity(int prec, int threads, int budget, int *cap)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const void *fn = jobs_fn_prec(prec);
+    HIPCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, budget));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, budget));
+    *cap = per_cu * cus;
+    return PT_OK;
+}
+
+void job_slot(JobSlot &S, const pt_job_desc &j, int prec, unsigned char *base, const double *Tdev,
+              const LdsPlan &plan, int32_t variant, int32_t wbase)
+{
+    const Layout lay = layout_of(j.L, j.q, j.R, prec, 0, kJobEvents);
+    std::memset(&S, 0, sizeof S);
+    fill_inst(S.inst, base, lay, j.L, j.q, j.R, j.seed, prec == PT_PREC_F32 ? 32 : 0, 0, kJobEvents);
+    S.plan = plan;
+    S.T = Tdev;
+    S.sigma = j.sigma;
+    S.sweeps = j.sweeps;
+    S.xevery = j.exchange_every;
+    S.init = j.init;
+    S.wbase = wbase;
+    S.variant = variant;
+}
+
+void shape_defaults(const pt_options &o, int *threads, int *budget)
+{
+    *threads = o.threads ? o.threads : 128;
+    *budget = o.lds_budget > 0 ? o.lds_budget : 64 * 1024;
+}
+
+pt_status fetch_spins(const Inst &P, hipStream_t st, uint8_t *spins, int32_t *perm)
+{
+    const size_t n = static_cast<size_t>(P.R) * P.L;
+    if (spins) {
+        HIPCHK(hipMemcpyAsync(spins, P.spins, n, hipMemcpyDeviceToHost, st));
+    }
+    if (perm) HIPCHK(hipMemcpyAsync(perm, P.perm, sizeof(int32_t) * P.R, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (spins)
+        for (size_t e = 0; e < n; ++e) spins[e] = static_cast<uint8_t>(spins[e] + 1);
+    return PT_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// Batches
+// ===========================================================================
+struct pt_batch {
+    int32_t njobs = 0, prec = 0, threads = 128, budget = 0, grid = 0;
+    hipStream_t stream = nullptr;
+    unsigned char *ws = nullptr;
+    size_t ws_bytes = 0;
+    bool own_ws = false, ran = false;
+    std::vector<JobSlot> slots;
+    std::vector<pt_job_desc> jobs;
+    JobSlot *d_slots = nullptr;
+    JobControl *d_ctl = nullptr;
+    double *d_T = nullptr;
+    std::vector<double> Tall;
+    size_t slots_off = 0, ctl_off = 0, T_off = 0, total = 0;
+    std::vector<size_t> job_off;
+};
+
+namespace {
+
+pt_status batch_layout(const pt_job_desc *jobs, int32_t n, const pt_options &o, pt_batch *b)
+{
+    if (!jobs || n < 1) return fail(PT_EINVAL, "no jobs");
+    if (o.precision != PT_PREC_F64 && o.precision != PT_PREC_F32) return fail(PT_EINVAL, "bad precision");
+    size_t off = 0, nT = 0;
+    b->job_off.resize(n);
+    for (int j = 0; j < n; ++j) {
+        const pt_status st = validate_job(jobs[j]);
+        if (st != PT_OK) return fail(st, "job %d: %s", j, pt_last_error());
+        b->job_off[j] = off;
+        off += job_bytes(jobs[j], o.precision);
+        nT += static_cast<size_t>(jobs[j].R);
+    }
+    b->slots_off = off;
+    off += Layout::up(sizeof(JobSlot) * n);
+    b->ctl_off = off;
+    off += Layout::up(sizeof(JobControl));
+    b->T_off = off;
+    off += Layout::up(sizeof(double) * nT);
+    b->total = off;
+    return PT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pt_status pt_batch_workspace_size(const pt_job_desc *jobs, int32_t njobs, const pt_options *opt, size_t *bytes)
+{
+    if (!bytes) return fail(PT_EINVAL, "bytes is NULL");
+    pt_options d;
+    pt_default_options(&d);
+    pt_batch tmp;
+    const pt_status st = batch_layout(jobs, njobs, opt ? *opt : d, &tmp);
+    if (st != PT_OK) return st;
+    *bytes = tmp.total;
+    return PT_OK;
+}
+
+pt_status pt_batch_create(pt_batch **out, const pt_job_desc *jobs, int32_t njobs, const pt_options *opt)
+{
+    if (!out) return fail(PT_EINVAL, "out is NULL");
+    *out = nullptr;
+    pt_options d;
+    pt_default_options(&d);
+    const pt_options &o = opt ? *opt : d;
+    pt_batch *b = new (std::nothrow) pt_batch();
+    if (!b) return fail(PT_ENOMEM, "host allocation failed");
+    auto bail = [&](pt_status st) {
+        if (b->own_ws && b->ws) (void)hipFree(b->ws);
+        delete b;
+        return st;
+    };
+    pt_status st = batch_layout(jobs, njobs, o, b);
+    if (st != PT_OK) return bail(st);
+    b->njobs = njobs;
+    b->prec = o.precision;
+    b->stream = static_cast<hipStream_t>(o.stream);
+    shape_defaults(o, &b->threads, &b->budget);
+    if (b->threads % kWave || b->threads < kWave || b->threads > kMaxSweepThreads)
+        return bail(fail(PT_EINVAL, "threads must be a multiple of 64 in [64, %d]", kMaxSweepThreads));
+    int lds_max = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return bail(fail(PT_EDEVICE, "device query failed"));
+    if (b->budget > lds_max || b->budget < 4096) return bail(fail(PT_EINVAL, "lds_budget must be in [4096, %d]", lds_max));
+    if (o.workspace) {
+        if (o.workspace_bytes < b->total) return bail(fail(PT_ENOMEM, "workspace of %zu B < %zu B", o.workspace_bytes, b->total));
+        b->ws = static_cast<unsigned char *>(o.workspace);
+        b->ws_bytes = o.workspace_bytes;
+    } else {
+        if (hipMalloc(&b->ws, b->total) != hipSuccess) return bail(fail(PT_ENOMEM, "hipMalloc(%zu) failed", b->total));
+        b->own_ws = true;
+        b->ws_bytes = b->total;
+    }
+    b->d_slots = reinterpret_cast<JobSlot *>(b->ws + b->slots_off);
+    b->d_ctl = reinterpret_cast<JobControl *>(b->ws + b->ctl_off);
+    b->d_T = reinterpret_cast<double *>(b->ws + b->T_off);
+    b->slots.resize(njobs);
+    b->jobs.assign(jobs, jobs + njobs);
+    int32_t wbase = 0, maxR = 0;
+    size_t toff = 0;
+    for (int j = 0; j < njobs; ++j) {
+        LdsPlan plan;
+        int32_t variant = 0;
+        if ((st = job_plan(jobs[j], b->prec, b->budget, &plan, &variant)) != PT_OK) return bail(st);
+        b->Tall.insert(b->Tall.end(), jobs[j].T, jobs[j].T + jobs[j].R);
+        job_slot(b->slots[j], jobs[j], b->prec, b->ws + b->job_off[j], b->d_T + toff, plan, variant, wbase);
+        b->jobs[j].T = nullptr;
+        toff += jobs[j].R;
+        wbase += jobs[j].R;
+        maxR = std::max(maxR, jobs[j].R);
+    }
+    int cap = 0;
+    if ((st = jobs_capacity(b->prec, b->threads, b->budget, &cap)) != PT_OK) return bail(st);
+    if (cap < maxR)
+        return bail(fail(PT_EINVAL, "only %d workgroups fit at once but a job has %d replicas", cap, maxR));
+    b->grid = std::min(cap, wbase);
+    *out = b;
+    return PT_OK;
+}
+
+pt_status pt_batch_run(pt_batch *b)
+{
+    if (!b) return fail(PT_EINVAL, "null batch");
+    if (b->ran) return fail(PT_ESTATE, "batch already ran");
+    HIPCHK(hipMemsetAsync(b->ws, 0, b->slots_off, b->stream));
+    HIPCHK(hipMemsetAsync(b->d_ctl, 0, sizeof(JobControl), b->stream));
+    HIPCHK(hipMemcpyAsync(b->d_slots, b->slots.data(), sizeof(JobSlot) * b->njobs, hipMemcpyHostToDevice, b->stream));
+    HIPCHK(hipMemcpyAsync(b->d_T, b->Tall.data(), sizeof(double) * b->Tall.size(), hipMemcpyHostToDevice, b->stream));
+    const JobSlot *slots = b->d_slots;
+    int32_t nstatic = b->njobs;
+    const int32_t *pub = nullptr, *stop = nullptr;
+    JobControl *ctl = b->d_ctl;
+    int32_t *done = nullptr;
+    void *args[] = {&slots, &nstatic, &pub, &stop, &ctl, &done};
+    HIPCHK(hipLaunchKernel(jobs_fn_prec(b->prec), dim3(b->grid), dim3(b->threads), args, b->budget, b->stream));
+    b->ran = true;
+    return PT_OK;
+}
+
+pt_status pt_batch_observables(pt_batch *b, int32_t job, pt_obs *out)
+{
+    if (!b || !out) return fail(PT_EINVAL, "null argument");
+    if (job < 0 || job >= b->njobs) return fail(PT_EINVAL, "job index out of range");
+    HIPCHK(hipStreamSynchronize(b->stream));
+    HostObs h;
+    const pt_status st = h.fetch(b->slots[job].inst, b->stream);
+    if (st != PT_OK) return st;
+    if (h.ctr[kCtrError]) return fail(PT_EDEVICE, "job %d reported error bits 0x%llx", job, h.ctr[kCtrError]);
+    const int64_t sw = b->ran ? b->jobs[job].sweeps : 0;
+    h.fill(out, sw, sw / b->jobs[job].exchange_every, sw);
+    return PT_OK;
+}
+
+pt_status pt_batch_get_spins(pt_batch *b, int32_t job, uint8_t *spins, int32_t *perm)
+{
+    if (!b) return fail(PT_EINVAL, "null batch");
+    if (job < 0 || job >= b->njobs) return fail(PT_EINVAL, "job index out of range");
+    HIPCHK(hipStreamSynchronize(b->stream));
+    return fetch_spins(b->slots[job].inst, b->stream, spins, perm);
+}
+
+pt_status pt_batch_shape(pt_batch *b, int32_t *wgs, int32_t *threads, int32_t *lds)
+{
+    if (!b) return fail(PT_EINVAL, "null batch");
+    if (wgs) *wgs = b->grid;
+    if (threads) *threads = b->threads;
+    if (lds) *lds = b->budget;
+    return PT_OK;
+}
+
+pt_status pt_batch_free(pt_batch *b)
+{
+    if (!b) return fail(PT_EINVAL, "null batch");
+    (void)hipStreamSynchronize(b->stream);
+    if (b->own_ws && b->ws) (void)hipFree(b->ws);
+    delete b;
+    return PT_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Server
+// ===========================================================================
+struct ServerJob {
+    pt_job_desc desc{};
+    std::vector<double> T;
+    int64_t id = 0;
+    int32_t slot = -1;          // index in the job table once admitted
+    size_t off = 0, bytes = 0;  // arena block
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    int state = 0;              // 0 queued, 1 running, 2 done, 3 failed
+    HostObs obs;
+    std::vector<uint8_t> spins;
+};
+
+struct pt_server {
+    int32_t prec = 0, threads = 128, budget = 0, grid = 0, max_jobs = 0;
+    size_t arena_bytes = 0;
+    unsigned char *mem = nullptr;   // device: arena | slots | control | temperatures
+    bool own_mem = false;
+    size_t slots_off = 0, ctl_off = 0, T_off = 0;
+    JobSlot *d_slots = nullptr;
+    JobControl *d_ctl = nullptr;
+    double *d_T = nullptr;          // [max_jobs][64] temperatures
+    int32_t *h_ctl = nullptr;       // pinned: [0] published, [1] stop
+    int32_t *h_done = nullptr;      // pinned: [max_jobs]
+    JobSlot *h_slot = nullptr;      // pinned staging for one slot
+    double *h_T = nullptr;          // pinned staging for one ladder
+    unsigned long long *h_zero = nullptr;
+    hipStream_t kstream = nullptr, cstream = nullptr;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<int64_t> queue;
+    std::map<int64_t, ServerJob> jobs;
+    std::vector<int64_t> running;
+    std::map<size_t, size_t> free_blocks;  // offset -> bytes
+    int64_t next_id = 0;
+    int32_t published = 0;
+    int32_t wbase = 0;
+    bool quit = false, failed = false;
+    std::string fail_msg;
+    std::thread th;
+    double t0 = 0;
+};
+
+namespace {
+
+constexpr int kServerMaxR = 64;
+
+bool arena_alloc(pt_server *s, size_t bytes, size_t *off)
+{
+    for (auto it = s->free_blocks.begin(); it != s->free_blocks.end(); ++it) {
+        if (it->second >= bytes) {
+            *off = it->first;
+            const size_t rest = it->second - bytes;
+            const size_t at = it->first + bytes;
+            s->free_blocks.erase(it);
+            if (rest) s->free_blocks[at] = rest;
+            return true;
+        }
+    }
+    return false;
+}
+
+void arena_free(pt_server *s, size_t off, size_t bytes)
+{
+    auto it = s->free_blocks.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != s->free_blocks.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        s->free_blocks.erase(nx);
+    }
+    if (it != s->free_blocks.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            s->free_blocks.erase(it);
+        }
+    }
+}
+
+// Admit the queue's head jobs that fit, in order; publish them.
+bool server_admit(pt_server *s, std::unique_lock<std::mutex> &lk)
+{
+    bool any = false;
+    while (!s->queue.empty() && s->published < s->max_jobs) {
+        ServerJob &J = s->jobs[s->queue.front()];
+        size_t off = 0;
+        if (!arena_alloc(s, J.bytes, &off)) break;  // head-of-line: wait for memory
+        s->queue.pop_front();
+        J.off = off;
+        J.slot = s->published;
+        LdsPlan plan;
+        int32_t variant = 0;
+        job_plan(J.desc, s->prec, s->budget, &plan, &variant);
+        const double *Tdev = s->d_T + static_cast<size_t>(J.slot) * kServerMaxR;
+        job_slot(*s->h_slot, J.desc, s->prec, s->mem + off, Tdev, plan, variant, s->wbase);
+        std::memcpy(s->h_T, J.T.data(), sizeof(double) * J.desc.R);
+        lk.unlock();
+        const Inst &P = s->h_slot->inst;
+        bool ok = hipMemcpyAsync(P.ctr, s->h_zero, sizeof(unsigned long long) * kCtrN, hipMemcpyHostToDevice,
+                                 s->cstream) == hipSuccess &&
+                  hipMemcpyAsync(const_cast<double *>(Tdev), s->h_T, sizeof(double) * J.desc.R,
+                                 hipMemcpyHostToDevice, s->cstream) == hipSuccess &&
+                  hipMemcpyAsync(s->d_slots + J.slot, s->h_slot, sizeof(JobSlot), hipMemcpyHostToDevice,
+                                 s->cstream) == hipSuccess &&
+                  hipStreamSynchronize(s->cstream) == hipSuccess;
+        lk.lock();
+        if (!ok) {
+            s->failed = true;
+            s->fail_msg = "copy to the device failed";
+            return any;
+        }
+        s->wbase += J.desc.R;
+        s->published += 1;
+        J.state = 1;
+        J.t_admit = now_s() - s->t0;
+        s->running.push_back(J.id);
+        __atomic_store_n(&s->h_ctl[0], s->published, __ATOMIC_RELEASE);
+        any = true;
+    }
+    return any;
+}
+
+// Collect jobs whose last walker has finished.
+bool server_collect(pt_server *s, std::unique_lock<std::mutex> &lk)
+{
+    bool any = false;
+    for (size_t k = 0; k < s->running.size();) {
+        ServerJob &J = s->jobs[s->running[k]];
+        if (__atomic_load_n(&s->h_done[J.slot], __ATOMIC_ACQUIRE) == 0) {
+            ++k;
+            continue;
+        }
+        JobSlot S;
+        const Layout lay = layout_of(J.desc.L, J.desc.q, J.desc.R, s->prec, 0, kJobEvents);
+        fill_inst(S.inst, s->mem + J.off, lay, J.desc.L, J.desc.q, J.desc.R, J.desc.seed, 0, 0, kJobEvents);
+        lk.unlock();
+        J.spins.resize(static_cast<size_t>(J.desc.R) * J.desc.L);
+        const bool ok = J.obs.fetch(S.inst, s->cstream) == PT_OK &&
+                        hipMemcpyAsync(J.spins.data(), S.inst.spins, J.spins.size(), hipMemcpyDeviceToHost,
+                                       s->cstream) == hipSuccess &&
+                        hipStreamSynchronize(s->cstream) == hipSuccess;
+        lk.lock();
+        J.t_done = now_s() - s->t0;
+        J.state = ok && J.obs.ctr[kCtrError] == 0 ? 2 : 3;
+        arena_free(s, J.off, J.bytes);
+        s->running.erase(s->running.begin() + static_cast<long>(k));
+        any = true;
+    }
+    return any;
+}
+
+void server_loop(pt_server *s)
+{
+    std::unique_lock<std::mutex> lk(s->mu);
+    while (!s->failed) {
+        const bool a = server_admit(s, lk);
+        const bool c = server_collect(s, lk);
+        if (a || c) s->cv.notify_all();
+        if (s->quit && s->queue.empty() && s->running.empty()) break;
+        s->cv.wait_for(lk, std::chrono::microseconds(200));
+    }
+    s->cv.notify_all();
+}
+
+}  // namespace
+
+extern "C" {
+
+pt_status pt_server_start(pt_server **out, size_t arena_bytes, int32_t max_jobs, const pt_options *opt)
+{
+    if (!out) return fail(PT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (max_jobs < 1 || arena_bytes < 4096) return fail(PT_EINVAL, "bad arena size or job count");
+    pt_options d;
+    pt_default_options(&d);
+    const pt_options &o = opt ? *opt : d;
+    if (o.precision != PT_PREC_F64 && o.precision != PT_PREC_F32) return fail(PT_EINVAL, "bad precision");
+    pt_server *s = new (std::nothrow) pt_server();
+    if (!s) return fail(PT_ENOMEM, "host allocation failed");
+    auto bail = [&](pt_status st) {
+        if (s->kstream) (void)hipStreamDestroy(s->kstream);
+        if (s->cstream) (void)hipStreamDestroy(s->cstream);
+        if (s->own_mem && s->mem) (void)hipFree(s->mem);
+        if (s->h_ctl) (void)hipHostFree(s->h_ctl);
+        if (s->h_done) (void)hipHostFree(s->h_done);
+        if (s->h_slot) (void)hipHostFree(s->h_slot);
+        if (s->h_T) (void)hipHostFree(s->h_T);
+        if (s->h_zero) (void)hipHostFree(s->h_zero);
+        delete s;
+        return st;
+    };
+    s->prec = o.precision;
+    s->max_jobs = max_jobs;
+    shape_defaults(o, &s->threads, &s->budget);
+    s->arena_bytes = Layout::up(arena_bytes);
+    s->slots_off = s->arena_bytes;
+    s->ctl_off = s->slots_off + Layout::up(sizeof(JobSlot) * static_cast<size_t>(max_jobs));
+    s->T_off = s->ctl_off + Layout::up(sizeof(JobControl));
+    const size_t total = s->T_off + Layout::up(sizeof(double) * kServerMaxR * static_cast<size_t>(max_jobs));
+    if (o.workspace) {
+        if (o.workspace_bytes < total) return bail(fail(PT_ENOMEM, "workspace of %zu B < %zu B", o.workspace_bytes, total));
+        s->mem = static_cast<unsigned char *>(o.workspace);
+    } else {
+        if (hipMalloc(&s->mem, total) != hipSuccess) return bail(fail(PT_ENOMEM, "hipMalloc(%zu) failed", total));
+        s->own_mem = true;
+    }
+    s->d_slots = reinterpret_cast<JobSlot *>(s->mem + s->slots_off);
+    s->d_ctl = reinterpret_cast<JobControl *>(s->mem + s->ctl_off);
+    s->d_T = reinterpret_cast<double *>(s->mem + s->T_off);
+    if (hipHostMalloc(&s->h_ctl, 256, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&s->h_done, sizeof(int32_t) * max_jobs, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&s->h_slot, sizeof(JobSlot), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&s->h_T, sizeof(double) * kServerMaxR, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&s->h_zero, sizeof(unsigned long long) * kCtrN, hipHostMallocDefault) != hipSuccess)
+        return bail(fail(PT_ENOMEM, "pinned host allocation failed"));
+    std::memset(s->h_ctl, 0, 256);
+    std::memset(s->h_done, 0, sizeof(int32_t) * max_jobs);
+    std::memset(s->h_zero, 0, sizeof(unsigned long long) * kCtrN);
+    if (hipStreamCreateWithFlags(&s->kstream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&s->cstream, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(PT_EDEVICE, "stream creation failed"));
+    int cap = 0;
+    pt_status st = jobs_capacity(s->prec, s->threads, s->budget, &cap);
+    if (st != PT_OK) return bail(st);
+    if (cap < kServerMaxR) return bail(fail(PT_EINVAL, "only %d workgroups fit at once (need %d)", cap, kServerMaxR));
+    s->grid = cap;
+    s->free_blocks[0] = s->arena_bytes;
+    if (hipMemsetAsync(s->d_ctl, 0, sizeof(JobControl), s->kstream) != hipSuccess)
+        return bail(fail(PT_EDEVICE, "memset failed"));
+    const JobSlot *slots = s->d_slots;
+    int32_t nstatic = -1;
+    const int32_t *pub = s->h_ctl, *stop = s->h_ctl + 1;
+    JobControl *ctl = s->d_ctl;
+    int32_t *done = s->h_done;
+    void *args[] = {&slots, &nstatic, &pub, &stop, &ctl, &done};
+    if (hipLaunchKernel(jobs_fn_prec(s->prec), dim3(s->grid), dim3(s->threads), args, s->budget, s->kstream) !=
+        hipSuccess)
+        return bail(fail(PT_EDEVICE, "server launch failed"));
+    s->t0 = now_s();
+    s->th = std::thread(server_loop, s);
+    *out = s;
+    return PT_OK;
+}
+
+pt_status pt_server_submit(pt_server *s, const pt_job_desc *job, int64_t *id_out)
+{
+    if (!s || !job) return fail(PT_EINVAL, "null argument");
+    pt_status st = validate_job(*job);
+    if (st != PT_OK) return st;
+    if (job->R > kServerMaxR) return fail(PT_EINVAL, "server jobs have at most %d replicas", kServerMaxR);
+    LdsPlan plan;
+    int32_t variant = 0;
+    if ((st = job_plan(*job, s->prec, s->budget, &plan, &variant)) != PT_OK) return st;
+    const size_t bytes = job_bytes(*job, s->prec);
+    if (bytes > s->arena_bytes) return fail(PT_ENOMEM, "job needs %zu B, arena has %zu B", bytes, s->arena_bytes);
+    std::lock_guard<std::mutex> g(s->mu);
+    if (s->failed) return fail(PT_EDEVICE, "server failed: %s", s->fail_msg.c_str());
+    if (s->quit) return fail(PT_ESTATE, "server is stopping");
+    if (s->next_id >= s->max_jobs) return fail(PT_ENOMEM, "server job table full (%d jobs)", s->max_jobs);
+    ServerJob J;
+    J.desc = *job;
+    J.T.assign(job->T, job->T + job->R);
+    J.desc.T = nullptr;
+    J.id = s->next_id++;
+    J.bytes = bytes;
+    J.t_submit = now_s() - s->t0;
+    s->jobs[J.id] = std::move(J);
+    s->queue.push_back(s->next_id - 1);
+    if (id_out) *id_out = s->next_id - 1;
+    s->cv.notify_all();
+    return PT_OK;
+}
+
+static pt_status server_result(pt_server *s, const ServerJob &J, pt_obs *out)
+{
+    if (J.state == 3) return fail(PT_EDEVICE, "job %lld failed on the device", static_cast<long long>(J.id));
+    if (out) J.obs.fill(out, J.desc.sweeps, J.desc.sweeps / J.desc.exchange_every, J.desc.sweeps);
+    (void)s;
+    return PT_OK;
+}
+
+pt_status pt_server_poll(pt_server *s, int64_t id, int32_t *done, pt_obs *out)
+{
+    if (!s) return fail(PT_EINVAL, "null server");
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->jobs.find(id);
+    if (it == s->jobs.end()) return fail(PT_EINVAL, "unknown job id");
+    const bool fin = it->second.state >= 2;
+    if (done) *done = fin ? 1 : 0;
+    if (fin) return server_result(s, it->second, out);
+    return PT_OK;
+}
+
+pt_status pt_server_wait(pt_server *s, int64_t id, double timeout_s, pt_obs *out)
+{
+    if (!s) return fail(PT_EINVAL, "null server");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->jobs.find(id);
+    if (it == s->jobs.end()) return fail(PT_EINVAL, "unknown job id");
+    const auto until = std::chrono::steady_clock::now() + std::chrono::duration<double>(timeout_s);
+    while (it->second.state < 2) {
+        if (s->failed) return fail(PT_EDEVICE, "server failed: %s", s->fail_msg.c_str());
+        if (s->cv.wait_until(lk, until) == std::cv_status::timeout && it->second.state < 2)
+            return fail(PT_ESTATE, "job %lld not finished after %.1f s", static_cast<long long>(id), timeout_s);
+    }
+    return server_result(s, it->second, out);
+}
+
+pt_status pt_server_times(pt_server *s, int64_t id, double *sub, double *adm, double *fin)
+{
+    if (!s) return fail(PT_EINVAL, "null server");
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->jobs.find(id);
+    if (it == s->jobs.end()) return fail(PT_EINVAL, "unknown job id");
+    if (sub) *sub = it->second.t_submit;
+    if (adm) *adm = it->second.t_admit;
+    if (fin) *fin = it->second.t_done;
+    return PT_OK;
+}
+
+pt_status pt_server_get_spins(pt_server *s, int64_t id, uint8_t *spins, int32_t *perm)
+{
+    if (!s) return fail(PT_EINVAL, "null server");
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->jobs.find(id);
+    if (it == s->jobs.end()) return fail(PT_EINVAL, "unknown job id");
+    const ServerJob &J = it->second;
+    if (J.state != 2) return fail(PT_ESTATE, "job not finished");
+    if (spins)
+        for (size_t e = 0; e < J.spins.size(); ++e) spins[e] = static_cast<uint8_t>(J.spins[e] + 1);
+    if (perm) std::memcpy(perm, J.obs.perm.data(), sizeof(int32_t) * J.desc.R);
+    return PT_OK;
+}
+
+pt_status pt_server_stop(pt_server *s)
+{
+    if (!s) return fail(PT_EINVAL, "null server");
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->quit = true;
+        s->cv.notify_all();
+    }
+    if (s->th.joinable()) s->th.join();
+    __atomic_store_n(&s->h_ctl[1], 1, __ATOMIC_RELEASE);
+    const hipError_t e = hipStreamSynchronize(s->kstream);
+    const bool failed = s->failed;
+    (void)hipStreamDestroy(s->kstream);
+    (void)hipStreamDestroy(s->cstream);
+    if (s->own_mem && s->mem) (void)hipFree(s->mem);
+    (void)hipHostFree(s->h_ctl);
+    (void)hipHostFree(s->h_done);
+    (void)hipHostFree(s->h_slot);
+    (void)hipHostFree(s->h_T);
+    (void)hipHostFree(s->h_zero);
+    delete s;
+    if (e != hipSuccess) return fail(PT_EDEVICE, "server kernel: %s", hipGetErrorString(e));
+    if (failed) return fail(PT_EDEVICE, "server failed");
+    return PT_OK;
+}
+
+}  // extern "C"

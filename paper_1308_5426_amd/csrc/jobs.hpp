@@ -1,0 +1,197 @@
+// jobs.hpp -- one persistent launch for many instances ("jobs") of uneven size.
+//
+// Each workgroup repeatedly claims a ticket.  Tickets are numbered job by job
+// (job j owns tickets wbase_j .. wbase_j + R_j - 1, one per walker), so at any
+// time at most one job is partly claimed: every job with a lower ticket range
+// is fully claimed and runs to completion, freeing workgroups that then claim
+// the rest.  With at least max_j R_j workgroups resident, the per-job device
+// barriers therefore always fill and the launch cannot deadlock.
+//
+// A claimed walker sets up its own state: walker 0 computes the job's
+// couplings (eq. 6) and publishes them; every walker draws its initial spins,
+// builds its field table and runs the job's sweeps with the exchange after
+// each (the same code as a single instance).  The last walker to finish marks
+// the job done.  A static batch has a fixed job count; a server keeps
+// publishing jobs (the count lives in host-visible memory) until told to stop.
+#pragma once
+#include "sweep.hpp"
+
+namespace ptmi {
+
+enum : int32_t { kVarHLds = 1, kVarJ64Lds = 2, kVarRegFlush = 4 };
+
+struct alignas(256) JobSlot {
+    Inst inst;
+    LdsPlan plan;      // carve of this job inside the launch's LDS budget
+    const double *T;   // [R] ascending temperatures (device memory)
+    double sigma;
+    int64_t sweeps;
+    int32_t xevery;
+    int32_t init;
+    int32_t wbase;     // first ticket of the job
+    int32_t variant;   // kVar* bits
+};
+
+struct JobControl {
+    unsigned ticket;   // next ticket (device memory)
+    unsigned pad[63];
+};
+
+__device__ __forceinline__ int32_t load_published(const int32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Set-up and sweeps of walker w of job S, then the job's completion count.
+template <typename F, int QT, bool HLDS, bool J64L>
+__device__ __forceinline__ void run_job_walker(const JobSlot &S, int w, unsigned char *lds, int32_t *done_flag, int32_t *sflag)
+{
+    Inst P = S.inst;
+    const int tid = threadIdx.x, L = P.L, R = P.R;
+    if (w == 0) {
+        // the job's couplings, error bounds, ladder and zeroed accumulators
+        double part = 0.0;
+        for (int r = tid; r <= L / 2; r += blockDim.x) {
+            jstar_entry(L, S.sigma, r, const_cast<double *>(P.J64), const_cast<float *>(P.J32));
+            if (r > 0) part += (L - r != r) ? 2.0 * P.J64[r] : P.J64[r];
+        }
+        for (int k = tid; k < R; k += blockDim.x) {
+            const_cast<double *>(P.beta)[k] = 1.0 / S.T[k];
+            P.perm[k] = k;
+            P.slot_of[k] = k;
+            P.fatt[k] = 0; P.facc[k] = 0; P.xatt[k] = 0; P.xacc[k] = 0;
+            for (int a = 0; a < 6; ++a) P.acc6[a * R + k] = 0.0;
+        }
+        __syncthreads();
+        const double Ssum = block_sum(part, reinterpret_cast<double *>(lds));
+        if (tid == 0) {
+            *P.bnd = table_bounds(Ssum, P.J64[1], L, sizeof(F) == sizeof(float));
+            __threadfence();
+            __hip_atomic_store(&P.ctr[kCtrJobReady], 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    if (tid == 0) {
+        int ok = 1;
+        const uint64_t t0 = wall_clock64();
+        while (__hip_atomic_load(&P.ctr[kCtrJobReady], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0ull) {
+            __builtin_amdgcn_s_sleep(8);
+            if (wall_clock64() - t0 > kBarrierTicks) {
+                atomicOr(&P.ctr[kCtrError], kErrBarrierTimeout);
+                ok = 0;
+                break;
+            }
+        }
+        __threadfence();
+        sflag[0] = ok;
+    }
+    __syncthreads();
+    if (!sflag[0]) return;
+    P.bound_init = __hip_atomic_load(&P.bnd->init, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    P.bound_unit = __hip_atomic_load(&P.bnd->unit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    P.nupd_max = __hip_atomic_load(&P.bnd->nupd_max, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int j = tid; j < L; j += blockDim.x)
+        P.spins[static_cast<size_t>(w) * L + j] = initial_spin(P, w, j, S.init != 0);
+    __syncthreads();
+    {
+        Walker<F> W = carve<F, HLDS, J64L>(lds, S.plan, P, w);
+        load_walker<F>(P, W, S.plan, w);
+        const double E = refresh_fields<F>(P, W);
+        __syncthreads();
+        store_walker<F>(P, W, S.plan, w);
+        if (tid == 0) {
+            P.E[w] = E;
+            P.Eerr[w] = 0.0;
+            P.nupd[w] = 0;
+            int nmax = 0;
+            for (int k = 0; k < P.q; ++k) nmax = max(nmax, W.cnt[k]);
+            P.Mw[w] = (static_cast<double>(P.q) * nmax / L - 1.0) / (P.q - 1);
+        }
+        __syncthreads();
+    }
+    if (!run_walker<F, QT, HLDS, J64L>(P, S.plan, lds, w, 0, static_cast<int32_t>(S.sweeps), S.xevery, 0, true))
+        return;
+    if (tid == 0) {
+        __threadfence_system();
+        const unsigned long long d =
+            __hip_atomic_fetch_add(&P.ctr[kCtrJobDone], 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (done_flag && d == static_cast<unsigned long long>(P.R) - 1ull) {
+            __threadfence_system();
+            __hip_atomic_store(done_flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
+    __syncthreads();
+}
+
+template <typename F>
+__device__ __forceinline__ void dispatch_job_walker(const JobSlot &S, int w, unsigned char *lds, int32_t *done_flag, int32_t *sflag)
+{
+    const int v = S.variant;
+    if constexpr (sizeof(F) == sizeof(double)) {
+        switch (v & (kVarHLds | kVarRegFlush)) {
+        case kVarHLds | kVarRegFlush: run_job_walker<F, 4, true, true>(S, w, lds, done_flag, sflag); break;
+        case kVarHLds: run_job_walker<F, 0, true, true>(S, w, lds, done_flag, sflag); break;
+        case kVarRegFlush: run_job_walker<F, 4, false, true>(S, w, lds, done_flag, sflag); break;
+        default: run_job_walker<F, 0, false, true>(S, w, lds, done_flag, sflag); break;
+        }
+    } else {
+        switch (v & (kVarHLds | kVarJ64Lds | kVarRegFlush)) {
+        case kVarHLds | kVarJ64Lds | kVarRegFlush: run_job_walker<F, 4, true, true>(S, w, lds, done_flag, sflag); break;
+        case kVarHLds | kVarJ64Lds: run_job_walker<F, 0, true, true>(S, w, lds, done_flag, sflag); break;
+        case kVarHLds | kVarRegFlush: run_job_walker<F, 4, true, false>(S, w, lds, done_flag, sflag); break;
+        case kVarHLds: run_job_walker<F, 0, true, false>(S, w, lds, done_flag, sflag); break;
+        case kVarJ64Lds | kVarRegFlush: run_job_walker<F, 4, false, true>(S, w, lds, done_flag, sflag); break;
+        case kVarJ64Lds: run_job_walker<F, 0, false, true>(S, w, lds, done_flag, sflag); break;
+        case kVarRegFlush: run_job_walker<F, 4, false, false>(S, w, lds, done_flag, sflag); break;
+        default: run_job_walker<F, 0, false, false>(S, w, lds, done_flag, sflag); break;
+        }
+    }
+}
+
+// nstatic >= 0: a batch of nstatic jobs (slots in device memory); the launch
+// ends when every ticket is taken.  nstatic < 0: serving; *published (host
+// memory) counts the valid slots, *stop (host memory) ends the launch once no
+// published ticket is left.
+template <typename F>
+__global__ __launch_bounds__(kMaxSweepThreads) void k_jobs(const JobSlot *__restrict__ slots, int32_t nstatic,
+                                                           const int32_t *published, const int32_t *stop,
+                                                           JobControl *ctl, int32_t *done_flags)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ int32_t sh[4];
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) {
+            const int t = static_cast<int>(atomicAdd(&ctl->ticket, 1u));
+            int found = -1;
+            for (;;) {
+                const int npub = nstatic >= 0 ? nstatic : load_published(published);
+                // the job whose ticket range holds t: last slot with wbase <= t
+                int lo = 0, hi = npub - 1;
+                while (lo <= hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (slots[mid].wbase <= t) {
+                        found = mid;
+                        lo = mid + 1;
+                    } else {
+                        hi = mid - 1;
+                    }
+                }
+                if (found >= 0 && t >= slots[found].wbase + slots[found].inst.R) found = -1;
+                if (found >= 0 || nstatic >= 0) break;
+                if (__hip_atomic_load(stop, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) != 0 &&
+                    load_published(published) == npub)
+                    break;
+                __builtin_amdgcn_s_sleep(64);
+            }
+            sh[0] = found;
+            sh[1] = found >= 0 ? t - slots[found].wbase : 0;
+        }
+        __syncthreads();
+        const int j = sh[0], w = sh[1];
+        if (j < 0) return;
+        dispatch_job_walker<F>(slots[j], w, lds, done_flags ? done_flags + j : nullptr, sh + 2);
+        __syncthreads();
+    }
+}
+
+}  // namespace ptmi

@@ -13,7 +13,7 @@
 #include <vector>
 
 #include "ptmi.h"
-#include "sweep.hpp"
+#include "jobs.hpp"
 
 using namespace ptmi;
 
@@ -146,17 +146,35 @@ pt_status validate(int32_t L, int32_t q, double sigma, const double *T, int32_t 
     return PT_OK;
 }
 
-// Kernel variant by the number of states: per-lane field registers for up to
-// 4, 8 or 16 states.
-template <typename F>
-const void *sweep_fn(int q)
+// Kernel variant by the number of states (flush fields in registers for up to
+// 4 states, direct LDS updates beyond) and by where the field table and the
+// FP64 couplings live.
+template <typename F, bool HLDS, bool J64L>
+const void *sweep_fn_q(int q)
 {
-    if (q <= 4) return reinterpret_cast<const void *>(&k_sweep<F, 4>);
-    if (q <= 8) return reinterpret_cast<const void *>(&k_sweep<F, 8>);
-    return reinterpret_cast<const void *>(&k_sweep<F, 16>);
+    if (q <= 4) return reinterpret_cast<const void *>(&k_sweep<F, 4, HLDS, J64L>);
+    return reinterpret_cast<const void *>(&k_sweep<F, 0, HLDS, J64L>);
 }
 template <typename F>
-const void *refresh_fn() { return reinterpret_cast<const void *>(&k_refresh<F>); }
+const void *sweep_fn(int q, const LdsPlan &p)
+{
+    if constexpr (sizeof(F) == sizeof(double))  // FP64 couplings are the table's own, always in LDS
+        return p.h_in_lds ? sweep_fn_q<F, true, true>(q) : sweep_fn_q<F, false, true>(q);
+    else if (p.h_in_lds) return p.j64_in_lds ? sweep_fn_q<F, true, true>(q) : sweep_fn_q<F, true, false>(q);
+    return p.j64_in_lds ? sweep_fn_q<F, false, true>(q) : sweep_fn_q<F, false, false>(q);
+}
+template <typename F>
+const void *refresh_fn(const LdsPlan &p)
+{
+    if constexpr (sizeof(F) == sizeof(double))
+        return p.h_in_lds ? reinterpret_cast<const void *>(&k_refresh<F, true, true>)
+                          : reinterpret_cast<const void *>(&k_refresh<F, false, true>);
+    else if (p.h_in_lds)
+        return p.j64_in_lds ? reinterpret_cast<const void *>(&k_refresh<F, true, true>)
+                            : reinterpret_cast<const void *>(&k_refresh<F, true, false>);
+    return p.j64_in_lds ? reinterpret_cast<const void *>(&k_refresh<F, false, true>)
+                        : reinterpret_cast<const void *>(&k_refresh<F, false, false>);
+}
 
 pt_status set_lds_attr(const void *fn, int bytes)
 {
@@ -167,8 +185,10 @@ pt_status set_lds_attr(const void *fn, int bytes)
 template <typename F>
 pt_status launch_refresh(pt_ctx *c)
 {
-    hipLaunchKernelGGL(k_refresh<F>, dim3(c->R), dim3(c->NT), c->plan.total, c->stream, c->inst, c->plan);
-    HIPCHK(hipGetLastError());
+    Inst P = c->inst;
+    LdsPlan plan = c->plan;
+    void *args[] = {&P, &plan};
+    HIPCHK(hipLaunchKernel(refresh_fn<F>(plan), dim3(c->R), dim3(c->NT), args, plan.total, c->stream));
     return PT_OK;
 }
 
@@ -180,9 +200,9 @@ pt_status launch_sweep(pt_ctx *c, int64_t n0, int32_t nsw, int32_t xevery, int64
     int32_t fu = fused ? 1 : 0;
     void *args[] = {&P, &plan, &n0, &nsw, &xevery, &m0, &fu};
     if (fused)
-        HIPCHK(hipLaunchCooperativeKernel(sweep_fn<F>(c->q), dim3(c->R), dim3(c->NT), args, plan.total, c->stream));
+        HIPCHK(hipLaunchCooperativeKernel(sweep_fn<F>(c->q, plan), dim3(c->R), dim3(c->NT), args, plan.total, c->stream));
     else
-        HIPCHK(hipLaunchKernel(sweep_fn<F>(c->q), dim3(c->R), dim3(c->NT), args, plan.total, c->stream));
+        HIPCHK(hipLaunchKernel(sweep_fn<F>(c->q, plan), dim3(c->R), dim3(c->NT), args, plan.total, c->stream));
     return PT_OK;
 }
 
@@ -213,6 +233,96 @@ pt_status device_error(pt_ctx *c)
     return PT_OK;
 }
 
+// Points an instance's arrays into its workspace block.
+void fill_inst(Inst &P, unsigned char *b, const Layout &lay, int L, int q, int R, uint64_t seed, int refresh_every,
+               int ser_cap, int ev_cap)
+{
+    P = Inst{};
+    P.L = L; P.q = q; P.R = R; P.walker0 = 0;
+    P.key0 = static_cast<uint32_t>(seed);
+    P.key1 = static_cast<uint32_t>(seed >> 32);
+    P.refresh_every = refresh_every;
+    P.ser_cap = ser_cap;
+    P.J64 = reinterpret_cast<const double *>(b + lay.J64);
+    P.J32 = reinterpret_cast<const float *>(b + lay.J32);
+    P.spins = b + lay.spins;
+    P.h = b + lay.h;
+    P.E = reinterpret_cast<double *>(b + lay.E);
+    P.Eerr = reinterpret_cast<double *>(b + lay.Eerr);
+    P.nupd = reinterpret_cast<int64_t *>(b + lay.nupd);
+    P.counts = reinterpret_cast<int32_t *>(b + lay.counts);
+    P.Mw = reinterpret_cast<double *>(b + lay.Mw);
+    P.perm = reinterpret_cast<int32_t *>(b + lay.perm);
+    P.slot_of = reinterpret_cast<int32_t *>(b + lay.slot_of);
+    P.beta = reinterpret_cast<const double *>(b + lay.beta);
+    P.acc6 = reinterpret_cast<double *>(b + lay.acc6);
+    P.fatt = reinterpret_cast<int64_t *>(b + lay.fatt);
+    P.facc = reinterpret_cast<int64_t *>(b + lay.facc);
+    P.xatt = reinterpret_cast<int64_t *>(b + lay.xatt);
+    P.xacc = reinterpret_cast<int64_t *>(b + lay.xacc);
+    P.serE = reinterpret_cast<double *>(b + lay.serE);
+    P.serM = reinterpret_cast<double *>(b + lay.serM);
+    P.events = reinterpret_cast<Event *>(b + lay.events);
+    P.ev_cap = ev_cap;
+    P.ctr = reinterpret_cast<unsigned long long *>(b + lay.ctr);
+    P.bnd = reinterpret_cast<TableBounds *>(b + lay.bnd);
+}
+
+// Host copy of an instance's observables (by walker / slot as on the device).
+struct HostObs {
+    int R = 0, q = 0, L = 0;
+    std::vector<double> Ew, Mw, acc6;
+    std::vector<int32_t> perm;
+    std::vector<int64_t> fatt, facc, xatt, xacc;
+    std::vector<unsigned long long> ctr;
+    int ev_cap = 0;
+
+    pt_status fetch(const Inst &P, hipStream_t st)
+    {
+        R = P.R; q = P.q; L = P.L; ev_cap = P.ev_cap;
+        Ew.resize(R); Mw.resize(R); acc6.resize(6 * R); perm.resize(R);
+        fatt.resize(R); facc.resize(R); xatt.resize(R); xacc.resize(R); ctr.resize(kCtrN);
+        HIPCHK(hipMemcpyAsync(Ew.data(), P.E, sizeof(double) * R, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(Mw.data(), P.Mw, sizeof(double) * R, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(acc6.data(), P.acc6, sizeof(double) * 6 * R, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(perm.data(), P.perm, sizeof(int32_t) * R, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(fatt.data(), P.fatt, sizeof(int64_t) * R, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(facc.data(), P.facc, sizeof(int64_t) * R, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(xatt.data(), P.xatt, sizeof(int64_t) * R, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(xacc.data(), P.xacc, sizeof(int64_t) * R, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(ctr.data(), P.ctr, sizeof(unsigned long long) * kCtrN, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return PT_OK;
+    }
+
+    void fill(pt_obs *o, int64_t sweeps, int64_t xsteps, int64_t samples) const
+    {
+        o->R = R; o->q = q; o->L = L;
+        o->sweeps = sweeps; o->exchange_steps = xsteps; o->samples = samples;
+        for (int k = 0; k < R; ++k) {
+            if (o->E) o->E[k] = Ew[perm[k]];
+            if (o->M) o->M[k] = Mw[perm[k]];
+            double *dst[6] = {o->sumE, o->sumE2, o->sumE4, o->sumM, o->sumM2, o->sumM4};
+            for (int a = 0; a < 6; ++a)
+                if (dst[a]) dst[a][k] = acc6[a * R + k];
+            if (o->flip_att) o->flip_att[k] = fatt[k];
+            if (o->flip_acc) o->flip_acc[k] = facc[k];
+            if (o->perm) o->perm[k] = perm[k];
+            if (k + 1 < R) {
+                if (o->xchg_att) o->xchg_att[k] = xatt[k];
+                if (o->xchg_acc) o->xchg_acc[k] = xacc[k];
+            }
+        }
+        o->n_recheck = static_cast<int64_t>(ctr[kCtrRecheck]);
+        o->n_banded = static_cast<int64_t>(ctr[kCtrBandedMet] + ctr[kCtrBandedEx]);
+        o->n_exact_energy = static_cast<int64_t>(ctr[kCtrExactE]);
+        o->n_refresh = static_cast<int64_t>(ctr[kCtrRefresh]);
+        o->n_events_dropped = ctr[kCtrEvents] > static_cast<unsigned long long>(ev_cap)
+                                  ? static_cast<int64_t>(ctr[kCtrEvents] - ev_cap)
+                                  : 0;
+    }
+};
+
 // Rigorous per-entry bounds of the field table (see the design notes): right
 // after a refresh the FP64 sum of at most L terms is rounded to the table's
 // precision; each applied flip adds one rounded coupling and one rounding.
@@ -223,13 +333,10 @@ void set_bounds(pt_ctx *c, const std::vector<double> &J)
         S += v;
         Jmax = std::max(Jmax, v);
     }
-    const double u64 = std::ldexp(1.0, -53);
-    const double uF = c->prec == PT_PREC_F32 ? std::ldexp(1.0, -24) : u64;
-    const double L = c->L;
-    c->inst.bound_init = (uF * S + (L + 4.0) * u64 * S) * 1.01 + 1e-15 * S;
-    c->inst.bound_unit = uF * (1.001 * S + 2.0 * Jmax) * 1.01 + u64 * S;
-    const double cap = 1e-3 * S / c->inst.bound_unit;
-    c->inst.nupd_max = cap > 4.0e18 ? static_cast<int64_t>(4e18) : static_cast<int64_t>(cap);
+    const TableBounds b = table_bounds(S, Jmax, c->L, c->prec == PT_PREC_F32);
+    c->inst.bound_init = b.init;
+    c->inst.bound_unit = b.unit;
+    c->inst.nupd_max = b.nupd_max;
 }
 
 }  // namespace
@@ -322,36 +429,10 @@ static pt_status init_impl(pt_ctx **out, int32_t L, int32_t q, double sigma, con
         c->own_ws = true;
         c->ws_bytes = lay.total;
     }
-    unsigned char *b = c->ws;
     Inst &P = c->inst;
-    P.L = L; P.q = q; P.R = R; P.walker0 = 0;
-    P.key0 = static_cast<uint32_t>(seed);
-    P.key1 = static_cast<uint32_t>(seed >> 32);
-    P.refresh_every = o.refresh_every > 0 ? o.refresh_every : (c->prec == PT_PREC_F32 ? 32 : 0);
+    fill_inst(P, c->ws, lay, L, q, R, seed, o.refresh_every > 0 ? o.refresh_every : (c->prec == PT_PREC_F32 ? 32 : 0),
+              c->ser_cap, c->ev_cap);
     c->refresh_every = P.refresh_every;
-    P.ser_cap = c->ser_cap;
-    P.J64 = reinterpret_cast<const double *>(b + lay.J64);
-    P.J32 = reinterpret_cast<const float *>(b + lay.J32);
-    P.spins = b + lay.spins;
-    P.h = b + lay.h;
-    P.E = reinterpret_cast<double *>(b + lay.E);
-    P.Eerr = reinterpret_cast<double *>(b + lay.Eerr);
-    P.nupd = reinterpret_cast<int64_t *>(b + lay.nupd);
-    P.counts = reinterpret_cast<int32_t *>(b + lay.counts);
-    P.Mw = reinterpret_cast<double *>(b + lay.Mw);
-    P.perm = reinterpret_cast<int32_t *>(b + lay.perm);
-    P.slot_of = reinterpret_cast<int32_t *>(b + lay.slot_of);
-    P.beta = reinterpret_cast<const double *>(b + lay.beta);
-    P.acc6 = reinterpret_cast<double *>(b + lay.acc6);
-    P.fatt = reinterpret_cast<int64_t *>(b + lay.fatt);
-    P.facc = reinterpret_cast<int64_t *>(b + lay.facc);
-    P.xatt = reinterpret_cast<int64_t *>(b + lay.xatt);
-    P.xacc = reinterpret_cast<int64_t *>(b + lay.xacc);
-    P.serE = reinterpret_cast<double *>(b + lay.serE);
-    P.serM = reinterpret_cast<double *>(b + lay.serM);
-    P.events = reinterpret_cast<Event *>(b + lay.events);
-    P.ev_cap = c->ev_cap;
-    P.ctr = reinterpret_cast<unsigned long long *>(b + lay.ctr);
 
     // hipMemset on the (possibly caller-provided) workspace: zero counters,
     // accumulators and the barrier words.
@@ -367,13 +448,14 @@ static pt_status init_impl(pt_ctx **out, int32_t L, int32_t q, double sigma, con
         hipMemcpyAsync(P.slot_of, ident.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice, c->stream) != hipSuccess)
         return bail(fail(PT_EDEVICE, "copy of ladder failed"));
 
-    const void *sf = c->prec == PT_PREC_F32 ? sweep_fn<float>(q) : sweep_fn<double>(q);
-    const void *rf = c->prec == PT_PREC_F32 ? refresh_fn<float>() : refresh_fn<double>();
-    const int lds_need = std::max(c->plan.total, fused_fits ? c->plan_fused.total : 0);
-    if (set_lds_attr(sf, lds_need) != PT_OK || set_lds_attr(rf, c->plan.total) != PT_OK) return bail(PT_EDEVICE);
+    const void *sf = c->prec == PT_PREC_F32 ? sweep_fn<float>(q, c->plan) : sweep_fn<double>(q, c->plan);
+    const void *rf = c->prec == PT_PREC_F32 ? refresh_fn<float>(c->plan) : refresh_fn<double>(c->plan);
+    if (set_lds_attr(sf, c->plan.total) != PT_OK || set_lds_attr(rf, c->plan.total) != PT_OK) return bail(PT_EDEVICE);
     if (fused_fits) {
+        const void *sff = c->prec == PT_PREC_F32 ? sweep_fn<float>(q, c->plan_fused) : sweep_fn<double>(q, c->plan_fused);
         int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sf, c->NT, c->plan_fused.total) == hipSuccess)
+        if (set_lds_attr(sff, c->plan_fused.total) == PT_OK &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sff, c->NT, c->plan_fused.total) == hipSuccess)
             c->can_fuse = static_cast<int64_t>(per_cu) * c->cus >= R;
     }
     c->max_chunk = o.max_sweeps_per_launch > 0 ? o.max_sweeps_per_launch : 1024;
@@ -480,44 +562,9 @@ pt_status pt_observables(pt_ctx *c, pt_obs *o)
     if (st != PT_OK) return st;
     if (!o) return fail(PT_EINVAL, "obs is NULL");
     if ((st = pt_synchronize(c)) != PT_OK) return st;
-    const int R = c->R;
-    const Inst &P = c->inst;
-    std::vector<double> Ew(R), Mw(R), acc6(6 * R);
-    std::vector<int32_t> perm(R);
-    std::vector<int64_t> fatt(R), facc(R), xatt(R), xacc(R);
-    std::vector<unsigned long long> ctr(kCtrN);
-    HIPCHK(hipMemcpy(Ew.data(), P.E, sizeof(double) * R, hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(Mw.data(), P.Mw, sizeof(double) * R, hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(acc6.data(), P.acc6, sizeof(double) * 6 * R, hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(perm.data(), P.perm, sizeof(int32_t) * R, hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(fatt.data(), P.fatt, sizeof(int64_t) * R, hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(facc.data(), P.facc, sizeof(int64_t) * R, hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(xatt.data(), P.xatt, sizeof(int64_t) * R, hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(xacc.data(), P.xacc, sizeof(int64_t) * R, hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(ctr.data(), P.ctr, sizeof(unsigned long long) * kCtrN, hipMemcpyDeviceToHost));
-    o->R = R; o->q = c->q; o->L = c->L;
-    o->sweeps = c->sweeps; o->exchange_steps = c->xsteps; o->samples = c->samples;
-    for (int k = 0; k < R; ++k) {
-        if (o->E) o->E[k] = Ew[perm[k]];
-        if (o->M) o->M[k] = Mw[perm[k]];
-        double *dst[6] = {o->sumE, o->sumE2, o->sumE4, o->sumM, o->sumM2, o->sumM4};
-        for (int a = 0; a < 6; ++a)
-            if (dst[a]) dst[a][k] = acc6[a * R + k];
-        if (o->flip_att) o->flip_att[k] = fatt[k];
-        if (o->flip_acc) o->flip_acc[k] = facc[k];
-        if (o->perm) o->perm[k] = perm[k];
-        if (k + 1 < R) {
-            if (o->xchg_att) o->xchg_att[k] = xatt[k];
-            if (o->xchg_acc) o->xchg_acc[k] = xacc[k];
-        }
-    }
-    o->n_recheck = static_cast<int64_t>(ctr[kCtrRecheck]);
-    o->n_banded = static_cast<int64_t>(ctr[kCtrBandedMet] + ctr[kCtrBandedEx]);
-    o->n_exact_energy = static_cast<int64_t>(ctr[kCtrExactE]);
-    o->n_refresh = static_cast<int64_t>(ctr[kCtrRefresh]);
-    o->n_events_dropped = ctr[kCtrEvents] > static_cast<unsigned long long>(c->ev_cap)
-                              ? static_cast<int64_t>(ctr[kCtrEvents] - c->ev_cap)
-                              : 0;
+    HostObs h;
+    if ((st = h.fetch(c->inst, c->stream)) != PT_OK) return st;
+    h.fill(o, c->sweeps, c->xsteps, c->samples);
     return PT_OK;
 }
 
@@ -692,3 +739,5 @@ pt_status pt_free(pt_ctx *c)
 }
 
 }  // extern "C"
+
+#include "host_jobs.hpp"

@@ -18,9 +18,33 @@ enum Counter : int {
     kCtrError = 6,       // error bits (kErr*)
     kCtrBarCount = 8,    // grid barrier arrivals (uint32 in the low word)
     kCtrBarGen = 9,      // grid barrier generation
+    kCtrJobReady = 10,   // job kernel: couplings and ladder of the job are ready
+    kCtrJobDone = 11,    // job kernel: walkers of the job that finished
     kCtrN = 16
 };
 enum : unsigned long long { kErrBarrierTimeout = 1ull, kErrBadLaunch = 2ull };
+
+// Rigorous per-entry error bounds of a field table (see sweep.hpp): right
+// after a refresh the FP64 sum of at most L couplings is rounded to the
+// table's precision; each flip applied since then adds one rounded coupling
+// and one rounding of the sum.  S = sum_r J*(r), Jmax = J*(1).  nupd_max caps
+// the number of flips between refreshes so the drift stays below 1e-3 S.
+struct TableBounds {
+    double init, unit;
+    int64_t nupd_max;
+};
+
+__host__ __device__ inline TableBounds table_bounds(double S, double Jmax, int L, bool f32)
+{
+    const double u64 = 0x1p-53;
+    const double uF = f32 ? 0x1p-24 : u64;
+    TableBounds b;
+    b.init = (uF * S + (static_cast<double>(L) + 4.0) * u64 * S) * 1.01 + 1e-15 * S;
+    b.unit = uF * (1.001 * S + 2.0 * Jmax) * 1.01 + u64 * S;
+    const double cap = 1e-3 * S / b.unit;
+    b.nupd_max = cap > 4.0e18 ? static_cast<int64_t>(4e18) : static_cast<int64_t>(cap);
+    return b;
+}
 
 struct Event {
     int64_t a, b, c;
@@ -56,11 +80,12 @@ struct Inst {
     Event *events;
     int32_t ev_cap;
     unsigned long long *ctr;   // [kCtrN]
+    TableBounds *bnd;          // bounds computed on the device (job kernel)
 };
 
 struct Layout {
     size_t J64, J32, spins, h, E, Eerr, nupd, counts, Mw, perm, slot_of, beta, acc6, fatt, facc,
-        xatt, xacc, serE, serM, events, ctr, total;
+        xatt, xacc, serE, serM, events, ctr, bnd, T, total;
 
     static size_t up(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
@@ -93,6 +118,8 @@ struct Layout {
         serM = take(sizeof(double) * static_cast<size_t>(ser_cap) * R);
         events = take(sizeof(Event) * static_cast<size_t>(ev_cap));
         ctr = take(sizeof(unsigned long long) * kCtrN);
+        bnd = take(sizeof(TableBounds));
+        T = take(sizeof(double) * R);
         total = o;
     }
 };

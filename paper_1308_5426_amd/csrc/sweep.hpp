@@ -68,14 +68,22 @@ struct Walker {
     int32_t chunk;
 };
 
-template <typename F>
+// HLDS / J64L: the field table / the FP64 couplings are in LDS.  They are
+// compile-time choices so that every access compiles to ds_* (LDS) or
+// global_* (HBM) instructions rather than flat ones.
+template <typename F, bool HLDS, bool J64L>
 __device__ __forceinline__ Walker<F> carve(unsigned char *lds, const LdsPlan &p, const Inst &P, int w)
 {
     Walker<F> W;
     W.J = reinterpret_cast<F *>(lds + p.J);
-    W.h = p.h_in_lds ? reinterpret_cast<F *>(lds + p.h)
-                     : static_cast<F *>(P.h) + static_cast<size_t>(w) * P.q * P.L;
-    W.J64 = p.j64_in_lds ? reinterpret_cast<const double *>(lds + p.J64) : P.J64;
+    if constexpr (HLDS)
+        W.h = reinterpret_cast<F *>(lds + p.h);
+    else
+        W.h = static_cast<F *>(P.h) + static_cast<size_t>(w) * P.q * P.L;
+    if constexpr (J64L)
+        W.J64 = reinterpret_cast<const double *>(lds + p.J64);
+    else
+        W.J64 = P.J64;
     W.sp = lds + p.sp;
     W.cnt = reinterpret_cast<int32_t *>(lds + p.cnt);
     W.masks = reinterpret_cast<uint64_t *>(lds + p.masks);
@@ -110,19 +118,20 @@ __device__ __forceinline__ void log_event(const Inst &P, int kind, int64_t a, in
 // ---------------------------------------------------------------------------
 // Initial spins (counter (j, 0, w, 2)) or the ordered state.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ uint8_t initial_spin(const Inst &P, int w, int j, bool ordered)
+{
+    if (ordered) return 0;
+    const uint4 o = philox10(make_uint4(static_cast<uint32_t>(j), 0u, static_cast<uint32_t>(w), 2u), P.key0, P.key1);
+    return static_cast<uint8_t>(__umulhi(o.x, static_cast<uint32_t>(P.q)));
+}
+
 __global__ void k_init_spins(Inst P, int32_t ordered)
 {
     const int64_t total = static_cast<int64_t>(P.R) * P.L;
     for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total;
          e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const int w = static_cast<int>(e / P.L), j = static_cast<int>(e % P.L);
-        uint8_t v = 0;
-        if (!ordered) {
-            const uint4 o = philox10(make_uint4(static_cast<uint32_t>(j), 0u, static_cast<uint32_t>(w), 2u),
-                                     P.key0, P.key1);
-            v = static_cast<uint8_t>(__umulhi(o.x, static_cast<uint32_t>(P.q)));
-        }
-        P.spins[e] = v;
+        P.spins[e] = initial_spin(P, w, j, ordered != 0);
     }
 }
 
@@ -130,7 +139,7 @@ __global__ void k_init_spins(Inst P, int32_t ordered)
 // Walker state HBM <-> LDS.
 // ---------------------------------------------------------------------------
 template <typename F>
-__device__ void load_walker(const Inst &P, Walker<F> &W, const LdsPlan &plan, int w)
+__device__ __forceinline__ void load_walker(const Inst &P, Walker<F> &W, const LdsPlan &plan, int w)
 {
     const int L = P.L, q = P.q;
     const F *Jsrc = coupling_src<F>(P);
@@ -148,7 +157,7 @@ __device__ void load_walker(const Inst &P, Walker<F> &W, const LdsPlan &plan, in
 }
 
 template <typename F>
-__device__ void store_walker(const Inst &P, const Walker<F> &W, const LdsPlan &plan, int w)
+__device__ __forceinline__ void store_walker(const Inst &P, const Walker<F> &W, const LdsPlan &plan, int w)
 {
     const int L = P.L, q = P.q;
     F *hdst = static_cast<F *>(P.h) + static_cast<size_t>(w) * q * L;
@@ -166,7 +175,7 @@ __device__ void store_walker(const Inst &P, const Walker<F> &W, const LdsPlan &p
 // energy E = -1/2 sum_j h[s_j][j] is formed from the FP64 sums.
 // ---------------------------------------------------------------------------
 template <typename F>
-__device__ double refresh_fields(const Inst &P, Walker<F> &W)
+__device__ __forceinline__ double refresh_fields(const Inst &P, Walker<F> &W)
 {
     const int L = P.L, q = P.q, tid = threadIdx.x, NT = blockDim.x;
     const int lane = tid & (kWave - 1), wv = tid / kWave, nw = NT / kWave;
@@ -410,7 +419,7 @@ __device__ __forceinline__ double rl_d(double v, int l)
 // Draws of attempts [c0, c0 + cnt) of sweep n (counter (t, n, w, 0)), staged
 // in LDS by the whole workgroup: site, state offset, ln u (FP64).
 template <typename F>
-__device__ void gen_draws(const Inst &P, Walker<F> &W, int w, int64_t n, int c0, int cnt)
+__device__ __forceinline__ void gen_draws(const Inst &P, Walker<F> &W, int w, int64_t n, int c0, int cnt)
 {
     for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
         const uint32_t t = static_cast<uint32_t>(c0 + e);
@@ -427,7 +436,7 @@ __device__ void gen_draws(const Inst &P, Walker<F> &W, int w, int64_t n, int c0,
 // change brought by each flip already accepted in this window (site ip went
 // from ap to bp, which changes its term by J*(|ip-i|) ([bp=a]-[bp=b]-[ap=a]+[ap=b])).
 template <typename F>
-__device__ double chain_direct_dE(const Walker<F> &W, int L, int i, int a, int b, int np)
+__device__ __forceinline__ double chain_direct_dE(const Walker<F> &W, int L, int i, int a, int b, int np)
 {
     const int lane = threadIdx.x & (kWave - 1);
     double part = 0.0;
@@ -481,7 +490,7 @@ __device__ __forceinline__ F field_now(const Walker<F> &W, int L, int c, int i, 
 // Each lane keeps only the two fields its attempt needs, ha = h[a][i] and
 // hb = h[b][i], and corrects them after every accepted flip.
 template <typename F>
-__device__ void chain_window(const Inst &P, Walker<F> &W, int w, int64_t n, double beta, int t0, int c0, int cend,
+__device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w, int64_t n, double beta, int t0, int c0, int cend,
                              ChainRegs &cr)
 {
     const int L = P.L, q = P.q, lane = threadIdx.x & (kWave - 1);
@@ -559,12 +568,16 @@ __device__ void chain_window(const Inst &P, Walker<F> &W, int w, int64_t n, doub
 }
 
 // Whole workgroup: apply the window's np flips to the table.  Each thread
-// holds up to 4 sites x q states in registers and applies the flips in
-// order.  With an FP32 table the same pass forms the exact FP64 energy change
+// owns up to 4 sites per pass and applies the flips to them in order, so no
+// barrier is needed between flips.  QT > 0: the sites' q <= QT fields sit in
+// registers for the pass (one table read and write per field); QT = 0: the
+// two rows a flip touches are updated in LDS directly (fewer registers, for
+// larger q).  The arithmetic per field is the same sequence either way.
+// With an FP32 table the same pass forms the exact FP64 energy change
 // of every flip, sum_j J*(|j-i|)[delta(a, s_j) - delta(b, s_j)], over the
 // spins as they were just before it (partial sums per thread).
 template <typename F, int QT>
-__device__ void flush_window(const Inst &P, Walker<F> &W, int np, double &part)
+__device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np, double &part)
 {
     constexpr int NJB = 4;
     constexpr bool kF32 = sizeof(F) == sizeof(float);
@@ -577,7 +590,7 @@ __device__ void flush_window(const Inst &P, Walker<F> &W, int np, double &part)
     for (int jb = 0; jb < L; jb += NT * NJB) {
         int jm[NJB];
         bool ok[NJB];
-        F hr[QT][NJB];
+        F hr[QT > 0 ? QT : 1][NJB];
         int sr[NJB];
 #pragma unroll
         for (int m = 0; m < NJB; ++m) {
@@ -590,6 +603,7 @@ __device__ void flush_window(const Inst &P, Walker<F> &W, int np, double &part)
         for (int c = 0; c < QT; ++c)
 #pragma unroll
             for (int m = 0; m < NJB; ++m) hr[c][m] = (c < q && ok[m]) ? W.h[c * L + jm[m]] : F(0);
+        (void)hr;
         for (int p = 0; p < np; ++p) {
             const uint32_t pk = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(W.pend[p])));
             const int ip = pk & 0xFFFF, ap = (pk >> 16) & 0xFF, bp = pk >> 24;
@@ -602,16 +616,26 @@ __device__ void flush_window(const Inst &P, Walker<F> &W, int np, double &part)
                 dd[m] = d;
                 jv[m] = W.J[d];
             }
+            if constexpr (QT > 0) {
 #pragma unroll
-            for (int c = 0; c < QT; ++c) {
-                if (c == ap) {
+                for (int c = 0; c < QT; ++c) {
+                    if (c == ap) {
 #pragma unroll
-                    for (int m = 0; m < NJB; ++m) hr[c][m] -= jv[m];
+                        for (int m = 0; m < NJB; ++m) hr[c][m] -= jv[m];
+                    }
+                    if (c == bp) {
+#pragma unroll
+                        for (int m = 0; m < NJB; ++m) hr[c][m] += jv[m];
+                    }
                 }
-                if (c == bp) {
+            } else {
+                F *ra = W.h + ap * L, *rb = W.h + bp * L;
 #pragma unroll
-                    for (int m = 0; m < NJB; ++m) hr[c][m] += jv[m];
-                }
+                for (int m = 0; m < NJB; ++m)
+                    if (ok[m]) {
+                        ra[jm[m]] -= jv[m];
+                        rb[jm[m]] += jv[m];
+                    }
             }
             if (kF32) {
 #pragma unroll
@@ -641,7 +665,7 @@ __device__ void flush_window(const Inst &P, Walker<F> &W, int np, double &part)
 // One sweep of walker w at sweep index n.  Returns this thread's part of the
 // exact energy change (FP32 table; zero otherwise).
 template <typename F, int QT>
-__device__ double sweep_walker(const Inst &P, Walker<F> &W, int w, int64_t n, double beta, ChainRegs &cr)
+__device__ __forceinline__ double sweep_walker(const Inst &P, Walker<F> &W, int w, int64_t n, double beta, ChainRegs &cr)
 {
     const int L = P.L, wave = threadIdx.x / kWave;
     double part = 0.0;
@@ -663,7 +687,7 @@ __device__ double sweep_walker(const Inst &P, Walker<F> &W, int w, int64_t n, do
 }
 
 template <typename F>
-__device__ void record_sweep(const Inst &P, const Walker<F> &W, int w, int slot, int64_t n, double E, int64_t nacc)
+__device__ __forceinline__ void record_sweep(const Inst &P, const Walker<F> &W, int w, int slot, int64_t n, double E, int64_t nacc)
 {
     if (threadIdx.x != 0) return;
     int nmax = 0;
@@ -689,12 +713,12 @@ __device__ void record_sweep(const Inst &P, const Walker<F> &W, int w, int slot,
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
-template <typename F>
+template <typename F, bool HLDS, bool J64L>
 __global__ __launch_bounds__(kMaxSweepThreads) void k_refresh(Inst P, LdsPlan plan)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     const int w = blockIdx.x;
-    Walker<F> W = carve<F>(lds, plan, P, w);
+    Walker<F> W = carve<F, HLDS, J64L>(lds, plan, P, w);
     load_walker<F>(P, W, plan, w);
     const double E = refresh_fields<F>(P, W);
     __syncthreads();
@@ -713,12 +737,12 @@ __global__ __launch_bounds__(kMaxSweepThreads) void k_refresh(Inst P, LdsPlan pl
 // load its state into LDS, sweep, record, refresh on schedule, and (fused)
 // meet the instance's other walkers at the device barrier for the exchange.
 // Returns false if the barrier timed out.
-template <typename F, int QT>
-__device__ bool run_walker(const Inst &P, const LdsPlan &plan, unsigned char *lds, int w, int64_t n0, int32_t nsw,
-                           int32_t xevery, int64_t m0, bool fused)
+template <typename F, int QT, bool HLDS, bool J64L>
+__device__ __forceinline__ bool run_walker(const Inst &P, const LdsPlan &plan, unsigned char *lds, int w, int64_t n0,
+                                           int32_t nsw, int32_t xevery, int64_t m0, bool fused)
 {
     const int tid = threadIdx.x;
-    Walker<F> W = carve<F>(lds, plan, P, w);
+    Walker<F> W = carve<F, HLDS, J64L>(lds, plan, P, w);
     load_walker<F>(P, W, plan, w);
     ChainRegs cr{P.E[w], P.Eerr[w], P.nupd[w], 0};
     int64_t m = m0;
@@ -780,12 +804,12 @@ __device__ bool run_walker(const Inst &P, const LdsPlan &plan, unsigned char *ld
     return true;
 }
 
-template <typename F, int QT>
+template <typename F, int QT, bool HLDS, bool J64L>
 __global__ __launch_bounds__(kMaxSweepThreads) void k_sweep(Inst P, LdsPlan plan, int64_t n0, int32_t nsw,
                                                             int32_t xevery, int64_t m0, int32_t fused)
 {
     extern __shared__ __align__(16) unsigned char lds[];
-    (void)run_walker<F, QT>(P, plan, lds, blockIdx.x, n0, nsw, xevery, m0, fused != 0);
+    (void)run_walker<F, QT, HLDS, J64L>(P, plan, lds, blockIdx.x, n0, nsw, xevery, m0, fused != 0);
 }
 
 __global__ __launch_bounds__(1024) void k_exchange(Inst P, int64_t m)
