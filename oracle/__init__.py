@@ -73,6 +73,8 @@ def _declare(L):
     L.orc_magnetization.argtypes = [_i32, _i32, _p]
     L.orc_pt_create.restype = _p
     L.orc_pt_create.argtypes = [_i32, _i32, _d, _p, _i32, _u64, _i32, _i32]
+    L.orc_pt_create_at.restype = _p
+    L.orc_pt_create_at.argtypes = [_i32, _i32, _d, _p, _i32, _u64, _i32, _i32, _i32]
     L.orc_pt_free.restype = None
     L.orc_pt_free.argtypes = [_p]
     L.orc_pt_set_threads.argtypes = [_p, _i32]
@@ -159,16 +161,17 @@ def ising_sweeps(J, sig, beta_ising, seed, walker, sweep0, nsweeps, E):
 class PT:
     """Oracle parallel-tempering run.  mode 0: direct O(L) dE per attempt;
     mode 1: FP64 field table.  init 0: uniform spins from the walker's
-    stream; init 1: all spins 1."""
+    stream; init 1: all spins 1.  wbase: walker k uses the stream of walker
+    wbase + k (to follow selected walkers of a larger run)."""
 
-    def __init__(self, L, q, sigma, T, seed, init=0, mode=0, threads=1, record=False):
+    def __init__(self, L, q, sigma, T, seed, init=0, mode=0, threads=1, record=False, wbase=0):
         T = np.ascontiguousarray(np.asarray(T, dtype=np.float64))
         self.L, self.q, self.R = int(L), int(q), len(T)
         self.sigma, self.seed = float(sigma), int(seed)
         self.T = T
         self._lib = lib()
-        self._h = self._lib.orc_pt_create(self.L, self.q, self.sigma, _ptr(T), self.R, self.seed,
-                                          int(init), int(mode))
+        self._h = self._lib.orc_pt_create_at(self.L, self.q, self.sigma, _ptr(T), self.R, self.seed,
+                                             int(init), int(mode), int(wbase))
         if not self._h:
             raise ValueError("oracle rejected the arguments")
         self._lib.orc_pt_set_threads(self._h, int(threads))

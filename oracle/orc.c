@@ -151,7 +151,7 @@ double orc_magnetization(int32_t L, int32_t q, const uint8_t *s)
 #define ORC_BAND 1e-9
 
 struct orc_pt {
-    int32_t L, q, R, mode, nthreads, record;
+    int32_t L, q, R, mode, nthreads, record, wbase;
     uint64_t seed;
     int64_t sweeps, xsteps;
     double *J;      /* [L] */
@@ -188,11 +188,19 @@ static void fields_from_spins(orc_pt *p, int32_t w)
 orc_pt *orc_pt_create(int32_t L, int32_t q, double sigma, const double *T, int32_t R, uint64_t seed,
                       int32_t init, int32_t mode)
 {
+    return orc_pt_create_at(L, q, sigma, T, R, seed, init, mode, 0);
+}
+
+/* As orc_pt_create, with walker k of this object taking the random stream of
+ * walker wbase + k (to follow selected walkers of a larger run). */
+orc_pt *orc_pt_create_at(int32_t L, int32_t q, double sigma, const double *T, int32_t R, uint64_t seed,
+                         int32_t init, int32_t mode, int32_t wbase)
+{
     if (L < 2 || q < 2 || q > 255 || !(sigma > 0.0) || R < 1 || !T) return NULL;
     for (int32_t k = 0; k < R; ++k)
         if (!(T[k] > 0.0) || !isfinite(T[k])) return NULL;
     orc_pt *p = (orc_pt *)calloc(1, sizeof *p);
-    p->L = L; p->q = q; p->R = R; p->mode = mode; p->seed = seed; p->nthreads = 1;
+    p->L = L; p->q = q; p->R = R; p->mode = mode; p->seed = seed; p->nthreads = 1; p->wbase = wbase;
     p->J = (double *)malloc(sizeof(double) * L);
     orc_jstar(L, sigma, p->J);
     p->beta = (double *)malloc(sizeof(double) * R);
@@ -203,7 +211,7 @@ orc_pt *orc_pt_create(int32_t L, int32_t q, double sigma, const double *T, int32
             uint8_t v = 1;
             if (init == 0) {
                 uint32_t o[4];
-                stream(seed, (uint32_t)j, 0u, (uint32_t)w, 2u, o);
+                stream(seed, (uint32_t)j, 0u, (uint32_t)(wbase + w), 2u, o);
                 v = (uint8_t)(1 + mulhi32(o[0], (uint32_t)q));
             }
             p->s[(size_t)w * L + j] = v;
@@ -287,7 +295,7 @@ static int64_t sweep_walker(orc_pt *p, int32_t w, int64_t n, int64_t *banded)
     int64_t acc = 0;
     for (int32_t t = 0; t < L; ++t) {
         uint32_t o[4];
-        stream(p->seed, (uint32_t)t, (uint32_t)n, (uint32_t)w, 0u, o);
+        stream(p->seed, (uint32_t)t, (uint32_t)n, (uint32_t)(p->wbase + w), 0u, o);
         const int32_t i = (int32_t)mulhi32(o[0], (uint32_t)L);
         const int32_t k = 1 + (int32_t)mulhi32(o[1], (uint32_t)(q - 1));
         const double u = unit_open(o[2], o[3]);

@@ -49,6 +49,8 @@ typedef struct orc_pt orc_pt;
 
 orc_pt *orc_pt_create(int32_t L, int32_t q, double sigma, const double *T, int32_t R,
                       uint64_t seed, int32_t init, int32_t mode);
+orc_pt *orc_pt_create_at(int32_t L, int32_t q, double sigma, const double *T, int32_t R, uint64_t seed,
+                         int32_t init, int32_t mode, int32_t wbase);
 void orc_pt_free(orc_pt *p);
 void orc_pt_set_threads(orc_pt *p, int32_t nthreads);  /* OpenMP threads over walkers */
 void orc_pt_record_series(orc_pt *p, int32_t on);       /* keep E, M per sweep and slot */

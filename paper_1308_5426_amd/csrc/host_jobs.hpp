@@ -86,10 +86,22 @@ void job_slot(JobSlot &S, const pt_job_desc &j, int prec, unsigned char *base, c
     S.variant = variant;
 }
 
-void shape_defaults(const pt_options &o, int *threads, int *budget)
+// Walker workgroup shape: threads, and LDS bytes per workgroup clamped to what
+// the device allows beside k_jobs' own static LDS.
+pt_status shape_defaults(const pt_options &o, int prec, int *threads, int *budget)
 {
     *threads = o.threads ? o.threads : 128;
-    *budget = o.lds_budget > 0 ? o.lds_budget : 64 * 1024;
+    int dev = 0, lds_max = 0;
+    hipFuncAttributes fa;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    HIPCHK(hipFuncGetAttributes(&fa, jobs_fn_prec(prec)));
+    const int cap = (lds_max - static_cast<int>(fa.sharedSizeBytes)) & ~255;
+    *budget = std::min(cap, o.lds_budget > 0 ? o.lds_budget : 64 * 1024);
+    if (*threads % kWave || *threads < kWave || *threads > kMaxSweepThreads)
+        return fail(PT_EINVAL, "threads must be a multiple of 64 in [64, %d]", kMaxSweepThreads);
+    if (*budget < 4096) return fail(PT_EINVAL, "lds_budget must be at least 4096 B");
+    return PT_OK;
 }
 
 pt_status fetch_spins(const Inst &P, hipStream_t st, uint8_t *spins, int32_t *perm)
@@ -186,14 +198,7 @@ pt_status pt_batch_create(pt_batch **out, const pt_job_desc *jobs, int32_t njobs
     b->njobs = njobs;
     b->prec = o.precision;
     b->stream = static_cast<hipStream_t>(o.stream);
-    shape_defaults(o, &b->threads, &b->budget);
-    if (b->threads % kWave || b->threads < kWave || b->threads > kMaxSweepThreads)
-        return bail(fail(PT_EINVAL, "threads must be a multiple of 64 in [64, %d]", kMaxSweepThreads));
-    int lds_max = 0, dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
-        return bail(fail(PT_EDEVICE, "device query failed"));
-    if (b->budget > lds_max || b->budget < 4096) return bail(fail(PT_EINVAL, "lds_budget must be in [4096, %d]", lds_max));
+    if ((st = shape_defaults(o, b->prec, &b->threads, &b->budget)) != PT_OK) return bail(st);
     if (o.workspace) {
         if (o.workspace_bytes < b->total) return bail(fail(PT_ENOMEM, "workspace of %zu B < %zu B", o.workspace_bytes, b->total));
         b->ws = static_cast<unsigned char *>(o.workspace);
@@ -486,7 +491,8 @@ pt_status pt_server_start(pt_server **out, size_t arena_bytes, int32_t max_jobs,
     };
     s->prec = o.precision;
     s->max_jobs = max_jobs;
-    shape_defaults(o, &s->threads, &s->budget);
+    pt_status st0 = shape_defaults(o, s->prec, &s->threads, &s->budget);
+    if (st0 != PT_OK) return bail(st0);
     s->arena_bytes = Layout::up(arena_bytes);
     s->slots_off = s->arena_bytes;
     s->ctl_off = s->slots_off + Layout::up(sizeof(JobSlot) * static_cast<size_t>(max_jobs));

@@ -462,8 +462,9 @@ __device__ __forceinline__ double chain_direct_dE(const Walker<F> &W, int L, int
 }
 
 struct ChainRegs {
-    double E, Eerr;
-    int64_t nupd, nacc;
+    double E, Eerr;     // walker energy and its error bound (workgroup-uniform)
+    int64_t nupd, nacc; // flips since the last refresh; accepts this sweep (wave 0)
+    double eL, errL;    // energy increments held by the accepting lanes (wave 0)
 };
 
 // Field of state c at site i as the chain sees it: the table entry (window
@@ -488,11 +489,18 @@ __device__ __forceinline__ F field_now(const Walker<F> &W, int L, int c, int i, 
 
 // Wave 0: the chain through attempts [t0, t0 + 64) (lanes past `cend` idle).
 // Each lane keeps only the two fields its attempt needs, ha = h[a][i] and
-// hb = h[b][i], and corrects them after every accepted flip.
+// hb = h[b][i], and corrects them after every accepted flip.  Two ballots
+// split the candidates into sure accepts (x < -trig) and near-threshold ones
+// (|x| <= trig, FP64 recheck); the first candidate is taken.  The coupling
+// row of the next candidate is fetched while the current flip is applied,
+// which hides the LDS latency whenever that candidate is the next accept.
+// Energy increments stay in the accepting lane (eL, errL) and are summed at
+// the end of the sweep.
 template <typename F>
-__device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w, int64_t n, double beta, int t0, int c0, int cend,
-                             ChainRegs &cr)
+__device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w, int64_t n, double beta, int t0,
+                                             int c0, int cend, ChainRegs &cr)
 {
+    constexpr bool kF64 = sizeof(F) == sizeof(double);
     const int L = P.L, q = P.q, lane = threadIdx.x & (kWave - 1);
     const int ta = t0 + lane;
     const bool valid = ta < cend;
@@ -506,25 +514,31 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
     F ha = W.h[a * L + i], hb = W.h[b * L + i];
     uint64_t live = __ballot(valid);
     int np = 0;
+    double Bd = 2.0 * (P.bound_init + static_cast<double>(cr.nupd) * P.bound_unit);
+    const double dBd = 2.0 * P.bound_unit;
+    int pf_site = -1;  // site whose coupling row pf_jv holds
+    F pf_jv = F(0);
     while (live) {
         const double dE = static_cast<double>(ha) - static_cast<double>(hb);
-        const double Bd = 2.0 * (P.bound_init + static_cast<double>(cr.nupd) * P.bound_unit);
-        const double trig = beta * Bd + kBand + kEvalMargin;
         const double x = beta * dE + lnu;
-        const uint64_t cand = __ballot(x < trig) & live;
+        const double trig = beta * Bd + kBand + kEvalMargin;
+        const uint64_t sure = __ballot(x < -trig) & live;
+        const uint64_t cand = (__ballot(x < trig) & live) | sure;
         if (cand == 0) break;
         const int f = __builtin_ctzll(cand);
-        const int i_f = rl_i(i, f), a_f = rl_i(a, f), b_f = rl_i(b, f);
-        const double x_f = rl_d(x, f);
+        const uint32_t pk = static_cast<uint32_t>(i) | (static_cast<uint32_t>(a) << 16) | (static_cast<uint32_t>(b) << 24);
+        const uint32_t pk_f = static_cast<uint32_t>(rl_i(static_cast<int>(pk), f));
+        const int i_f = static_cast<int>(pk_f & 0xFFFFu), a_f = static_cast<int>((pk_f >> 16) & 0xFFu),
+                  b_f = static_cast<int>(pk_f >> 24);
         bool accept = true;
-        double dEuse = rl_d(dE, f), errinc = Bd;
-        if (!(x_f < -trig)) {
+        double dEf = dE, errf = Bd;
+        if (!((sure >> f) & 1ull)) {
             // |x| inside the trigger band: decide with the FP64 direct sum
             const double d64 = chain_direct_dE(W, L, i_f, a_f, b_f, np);
             const double x64 = beta * d64 + rl_d(lnu, f);
             accept = x64 < 0.0;
-            dEuse = d64;
-            errinc = 0.0;
+            dEf = d64;
+            errf = 0.0;
             if (lane == 0) {
                 atomicAdd(&P.ctr[kCtrRecheck], 1ull);
                 if (fabs(x64) <= kBand) {
@@ -535,29 +549,44 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
         }
         if (accept) {
             if (lane == 0) {
-                W.pend[np] = static_cast<uint32_t>(i_f) | (static_cast<uint32_t>(a_f) << 16) |
-                             (static_cast<uint32_t>(b_f) << 24);
+                W.pend[np] = pk_f;
                 W.cnt[a_f] -= 1;
                 W.cnt[b_f] += 1;
             }
-            ++np;
-            if (sizeof(F) == sizeof(double)) {  // FP32 tables take E from the flush's exact sums
-                cr.E += dEuse;
-                cr.Eerr += errinc;
+            if (kF64 && lane == f) {  // FP32 tables take E from the flush's exact sums
+                cr.eL += dEf;
+                cr.errL += errf;
             }
+            ++np;
             ++cr.nupd;
             ++cr.nacc;
-            if (i == i_f) {
-                // this lane's own site changed state: its two fields are re-derived
+            Bd += dBd;
+            F jv;
+            if (i_f == pf_site) {
+                jv = pf_jv;
+            } else {
+                int d = i - i_f;
+                d += d < 0 ? L : 0;
+                jv = W.J[d];  // J*(0) = 0 on the flipped site itself
+            }
+            const uint64_t rest = f == kWave - 1 ? 0ull : cand & (~0ull << (f + 1));
+            if (rest) {
+                pf_site = rl_i(i, __builtin_ctzll(rest));
+                int d = i - pf_site;
+                d += d < 0 ? L : 0;
+                pf_jv = W.J[d];
+            } else {
+                pf_site = -1;
+            }
+            const bool later = f < kWave - 1 && ((live >> lane) & 1ull) && lane > f;
+            if (later && i == i_f) {
+                // a later attempt on the flipped site: its two fields are re-derived
                 a = b_f;
                 b = a + kk;
                 b -= b >= q ? q : 0;
                 ha = field_now(W, L, a, i, np);
                 hb = field_now(W, L, b, i, np);
             } else {
-                int d = i - i_f;
-                d += d < 0 ? L : 0;
-                const F jv = W.J[d];
                 ha = a == a_f ? ha - jv : (a == b_f ? ha + jv : ha);
                 hb = b == a_f ? hb - jv : (b == b_f ? hb + jv : hb);
             }
@@ -572,19 +601,22 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
 // barrier is needed between flips.  QT > 0: the sites' q <= QT fields sit in
 // registers for the pass (one table read and write per field); QT = 0: the
 // two rows a flip touches are updated in LDS directly (fewer registers, for
-// larger q).  The arithmetic per field is the same sequence either way.
-// With an FP32 table the same pass forms the exact FP64 energy change
-// of every flip, sum_j J*(|j-i|)[delta(a, s_j) - delta(b, s_j)], over the
-// spins as they were just before it (partial sums per thread).
+// larger q).  The arithmetic per field is the same sequence either way.  The
+// flip list is read once into a register (lane p holds flip p) and each
+// flip's couplings are loaded while the previous flip is applied.
+// With an FP32 table the same pass forms the exact FP64 energy change of
+// every flip, sum_j J*(|j-i|)[delta(a, s_j) - delta(b, s_j)], over the spins
+// as they were just before it (partial sums per thread).
 template <typename F, int QT>
 __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np, double &part)
 {
     constexpr int NJB = 4;
     constexpr bool kF32 = sizeof(F) == sizeof(float);
-    const int L = P.L, q = P.q, tid = threadIdx.x, NT = blockDim.x;
+    const int L = P.L, q = P.q, tid = threadIdx.x, NT = blockDim.x, lane = tid & (kWave - 1);
+    const uint32_t pv = lane < np ? W.pend[lane] : 0u;
     if (!kF32 && tid == 0)
         for (int p = 0; p < np; ++p) {
-            const uint32_t pk = W.pend[p];
+            const uint32_t pk = static_cast<uint32_t>(rl_i(static_cast<int>(pv), p));
             W.sp[pk & 0xFFFFu] = static_cast<uint8_t>(pk >> 24);
         }
     for (int jb = 0; jb < L; jb += NT * NJB) {
@@ -604,28 +636,50 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
 #pragma unroll
             for (int m = 0; m < NJB; ++m) hr[c][m] = (c < q && ok[m]) ? W.h[c * L + jm[m]] : F(0);
         (void)hr;
+        // couplings of flip 0
+        uint32_t pk = static_cast<uint32_t>(rl_i(static_cast<int>(pv), 0));
+        F jv[NJB];
+        double j64[NJB];
+        int dd[NJB];
+#pragma unroll
+        for (int m = 0; m < NJB; ++m) {
+            int d = jm[m] - static_cast<int>(pk & 0xFFFFu);
+            d += d < 0 ? L : 0;
+            dd[m] = d;
+            jv[m] = W.J[d];
+            j64[m] = kF32 ? W.J64[d] : 0.0;
+        }
         for (int p = 0; p < np; ++p) {
-            const uint32_t pk = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(W.pend[p])));
-            const int ip = pk & 0xFFFF, ap = (pk >> 16) & 0xFF, bp = pk >> 24;
-            F jv[NJB];
-            int dd[NJB];
+            const int ip = static_cast<int>(pk & 0xFFFFu), ap = static_cast<int>((pk >> 16) & 0xFFu),
+                      bp = static_cast<int>(pk >> 24);
+            F cj[NJB];
+            double c64[NJB];
 #pragma unroll
             for (int m = 0; m < NJB; ++m) {
-                int d = jm[m] - ip;
-                d += d < 0 ? L : 0;
-                dd[m] = d;
-                jv[m] = W.J[d];
+                cj[m] = jv[m];
+                c64[m] = j64[m];
+            }
+            if (p + 1 < np) {  // next flip's couplings in flight while this one is applied
+                pk = static_cast<uint32_t>(rl_i(static_cast<int>(pv), p + 1));
+#pragma unroll
+                for (int m = 0; m < NJB; ++m) {
+                    int d = jm[m] - static_cast<int>(pk & 0xFFFFu);
+                    d += d < 0 ? L : 0;
+                    dd[m] = d;
+                    jv[m] = W.J[d];
+                    j64[m] = kF32 ? W.J64[d] : 0.0;
+                }
             }
             if constexpr (QT > 0) {
 #pragma unroll
                 for (int c = 0; c < QT; ++c) {
                     if (c == ap) {
 #pragma unroll
-                        for (int m = 0; m < NJB; ++m) hr[c][m] -= jv[m];
+                        for (int m = 0; m < NJB; ++m) hr[c][m] -= cj[m];
                     }
                     if (c == bp) {
 #pragma unroll
-                        for (int m = 0; m < NJB; ++m) hr[c][m] += jv[m];
+                        for (int m = 0; m < NJB; ++m) hr[c][m] += cj[m];
                     }
                 }
             } else {
@@ -633,22 +687,20 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
 #pragma unroll
                 for (int m = 0; m < NJB; ++m)
                     if (ok[m]) {
-                        ra[jm[m]] -= jv[m];
-                        rb[jm[m]] += jv[m];
+                        ra[jm[m]] -= cj[m];
+                        rb[jm[m]] += cj[m];
                     }
             }
             if (kF32) {
 #pragma unroll
                 for (int m = 0; m < NJB; ++m) {
                     const int s = sr[m];
-                    if (s == ap || s == bp) {
-                        const double j64 = W.J64[dd[m]];
-                        part += s == ap ? j64 : -j64;
-                    }
+                    part += s == ap ? c64[m] : (s == bp ? -c64[m] : 0.0);
                     sr[m] = (ok[m] && jm[m] == ip) ? bp : s;
                 }
             }
         }
+        (void)dd;
 #pragma unroll
         for (int c = 0; c < QT; ++c)
 #pragma unroll
@@ -744,7 +796,7 @@ __device__ __forceinline__ bool run_walker(const Inst &P, const LdsPlan &plan, u
     const int tid = threadIdx.x;
     Walker<F> W = carve<F, HLDS, J64L>(lds, plan, P, w);
     load_walker<F>(P, W, plan, w);
-    ChainRegs cr{P.E[w], P.Eerr[w], P.nupd[w], 0};
+    ChainRegs cr{P.E[w], P.Eerr[w], P.nupd[w], 0, 0.0, 0.0};
     int64_t m = m0;
     __syncthreads();
     for (int s = 0; s < nsw; ++s) {
@@ -753,19 +805,16 @@ __device__ __forceinline__ bool run_walker(const Inst &P, const LdsPlan &plan, u
         const double beta = P.beta[slot];
         cr.nacc = 0;
         const double part = sweep_walker<F, QT>(P, W, w, n, beta, cr);
-        if (sizeof(F) == sizeof(float)) {
-            const double dEs = block_sum(part, W.red);  // exact FP64 energy change of the sweep
-            if (tid < kWave) cr.E += dEs;
-        }
+        // energy change of the sweep: the flush's exact sums (FP32 table) or
+        // the accepted flips' dE held by the chain lanes (FP64 table)
+        cr.E += block_sum(part + cr.eL, W.red);
+        cr.Eerr += block_sum(cr.errL, W.red);
+        cr.eL = cr.errL = 0.0;
         if (tid == 0) {
-            W.cs->E = cr.E;
-            W.cs->Eerr = cr.Eerr;
             W.cs->nupd = cr.nupd;
             W.cs->nacc = cr.nacc;
         }
         __syncthreads();
-        cr.E = W.cs->E;
-        cr.Eerr = W.cs->Eerr;
         cr.nupd = W.cs->nupd;
         cr.nacc = W.cs->nacc;
         record_sweep<F>(P, W, w, slot, n, cr.E, cr.nacc);

@@ -197,3 +197,27 @@ def test_invalid_arguments(pkg):
         with pytest.raises(pkg.PTError) as ei:
             pkg.Simulation(*args, 1)
         assert ei.value.status == pkg.PT_EINVAL
+
+
+def test_large_config_sampled(pkg, orc):
+    """L = 16384, q = 5, sigma = 0.3, 128 replicas geometric in [0.2, 2.5], ordered
+    start, FP32 table (too large for LDS, so its rows stay in HBM), at the real
+    launch shape: two sweeps of all walkers; walkers 0, 64 and 127 are followed
+    by the oracle on the same streams."""
+    from workloads import large
+
+    inst = large()
+    print(f"[parity] large L={inst.L} q={inst.q} R={inst.R}", flush=True)
+    sim = pkg.Simulation(inst.L, inst.q, inst.sigma, inst.T, inst.seed, precision=1, init=inst.init)
+    sim.sweep(2)
+    s, p = sim.spins()
+    obs = sim.observables()
+    np.testing.assert_array_equal(p, np.arange(inst.R))
+    ev = sim.events()
+    for w in (0, 64, 127):
+        ref = orc.PT(inst.L, inst.q, inst.sigma, [inst.T[w]], inst.seed, init=inst.init, mode=0, wbase=w)
+        ref.set_replay(met=[(0, b, c, d) for (k, a, b, c, d, _) in ev if k == 0 and a == w])
+        ref.sweep(2)
+        np.testing.assert_array_equal(s[w], ref.spins()[0])
+        assert obs["E"][w] == pytest.approx(ref.energies()[0], rel=1e-11)
+        assert obs["flip_acc"][w] == ref.stats()["flip_acc"][0]

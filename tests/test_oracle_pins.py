@@ -312,3 +312,15 @@ def test_equilibrium_against_full_enumeration(orc, mode):
         p = rates[k]
         err = math.sqrt(p * (1 - p) / st["xchg_att"][k]) * 3  # autocorrelation allowance
         assert abs(acc[k] - p) < 4.5 * err, (k, acc[k], p)
+
+
+def test_walker_offset_follows_the_larger_run(orc):
+    """A one-walker object with wbase = w reproduces walker w of a larger run
+    (same temperature, no exchange)."""
+    T = [0.5, 0.9, 1.4, 2.2]
+    big = orc.PT(30, 3, 0.6, T, 9, mode=0)
+    big.sweep(6)
+    for w in (1, 3):
+        one = orc.PT(30, 3, 0.6, [T[w]], 9, mode=0, wbase=w)
+        one.sweep(6)
+        np.testing.assert_array_equal(one.spins()[0], big.spins()[w])
