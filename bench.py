@@ -116,6 +116,120 @@ def cpu_baseline(inst, seconds=12.0, mode=0):
                       f"after each sweep), oracle mode: {what}, {dt:.1f} s"}
 
 
+def run_batch(args):
+    """256 uneven jobs in one persistent launch vs the plain per-instance form."""
+    import torch
+
+    import paper_1308_5426_amd as pkg
+    import workloads
+    from paper_1308_5426_amd import autotune
+
+    jobs = workloads.batch_jobs(n_jobs=args.jobs, sweeps=args.sweeps or 1000)
+    prec = 1 if args.precision == "f32" else 0
+    jd = [dict(L=j.L, q=j.q, sigma=j.sigma, T=j.T, seed=j.seed, sweeps=j.sweeps, exchange_every=1, init=0)
+          for j in jobs]
+    threads, lds = (autotune.tune(jd, precision=prec, verbose=True) if args.autotune else (0, 0))
+    attempts = sum(j.L * j.R * j.sweeps for j in jobs)
+    times, shape = [], None
+    for it in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b = pkg.Batch(jd, precision=prec, threads=threads, lds_budget=lds)
+        b.run()
+        acc = sum(int(b.observables(j)["flip_acc"].sum()) for j in range(len(jd)))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        shape = b.shape()
+        b.close()
+        if it >= args.warmup:
+            times.append(dt)
+    el = sum(times)
+    # plain per-instance GPU form: the same jobs one pt_init/pt_run at a time
+    k = min(args.plain_sample, len(jd))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in jd[:k]:
+        sim = pkg.Simulation(j["L"], j["q"], j["sigma"], j["T"], j["seed"], precision=prec)
+        sim.run(j["sweeps"], 1)
+        sim.observables()
+        sim.close()
+    dt_plain = time.perf_counter() - t0
+    att_plain = sum(j["L"] * len(j["T"]) * j["sweeps"] for j in jd[:k])
+    return {
+        "metric": "spin-flip attempts/sec (all replicas, batched)",
+        "value": attempts * args.steps / el, "unit": "attempts/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if prec else "f64", "data": "synthetic",
+        "config": {"workload": f"{len(jd)} jobs, L log-uniform [128, 8192], q in 2..10, sigma in [0.1, 1], "
+                               f"32 replicas geometric [0.2, 3.0], {jd[0]['sweeps']} sweeps, exchange every sweep",
+                   "jobs": len(jd), "walkers": sum(len(j["T"]) for j in jd), "attempts": attempts,
+                   "accept_fraction": acc / attempts, "shape": shape, "autotuned": bool(args.autotune)},
+        "plain_per_instance": {"value": att_plain / dt_plain, "unit": "attempts/s", "jobs_timed": k,
+                               "seconds": dt_plain},
+    }
+
+
+def run_serve(args):
+    """Poisson arrivals; each job submitted at its arrival time; time to result."""
+    import numpy as np
+    import torch
+
+    import paper_1308_5426_amd as pkg
+    import workloads
+
+    stream = workloads.serve_stream(rate=args.rate, duration=args.duration)
+    prec = 1 if args.precision == "f32" else 0
+    srv = pkg.Server(arena_bytes=int(args.arena_gb * (1 << 30)), max_jobs=len(stream) + 16, precision=prec,
+                     threads=args.threads, lds_budget=args.lds)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ids = []
+    for (ta, inst) in stream:
+        now = time.perf_counter() - t0
+        if ta > now:
+            time.sleep(ta - now)
+        ids.append((ta, inst, srv.submit(dict(L=inst.L, q=inst.q, sigma=inst.sigma, T=inst.T, seed=inst.seed,
+                                              sweeps=inst.sweeps, exchange_every=1, init=0))))
+        if len(ids) % 200 == 0:
+            print(f"[serve] submitted {len(ids)} at t={time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    lat, done_t, att = [], [], 0
+    for (ta, inst, jid) in ids:
+        srv.wait(jid, timeout=600)
+        sub, adm, fin = srv.times(jid)
+        lat.append(fin - sub)
+        done_t.append(fin)
+        att += inst.L * inst.R * inst.sweeps
+    span = max(done_t) - min(srv.times(j)[0] for (_, _, j) in ids)
+    srv.stop()
+    lat = np.array(lat)
+    return {
+        "metric": "spin-flip attempts/sec (all replicas, served); p50/p99 time-to-result",
+        "value": att / span, "unit": "attempts/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": span * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if prec else "f64", "data": "synthetic",
+        "config": {"workload": f"Poisson {args.rate:g} jobs/s for {args.duration:g} s; L log-uniform [64, 4096], "
+                               "q in 2..8, sigma in [0.1, 1], 16-64 replicas, 500-5000 sweeps",
+                   "jobs": len(ids), "attempts": att},
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                      "max": float(lat.max())},
+    }
+
+
+def lds_peak_measured():
+    """Aggregate LDS read bandwidth of the device from the probe library
+    (conflict-free 16-byte reads, 2 workgroups of 1024 threads per CU)."""
+    import ctypes
+
+    path = os.path.join(ROOT, "paper_1308_5426_amd", "libptmi_probe.so")
+    lib = ctypes.CDLL(path)
+    lib.ptmi_lds_read_bandwidth.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.POINTER(ctypes.c_double)]
+    bw = ctypes.c_double(0.0)
+    if lib.ptmi_lds_read_bandwidth(2 * CUS, 1024, 2000, ctypes.byref(bw)) != 0:
+        return None
+    return bw.value
+
+
 def load_traffic(sha, name):
     p = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(p):
@@ -132,7 +246,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="medium", choices=["small", "medium", "large"])
+    ap.add_argument("--workload", default="medium", choices=["small", "medium", "large", "batch", "serve"])
+    ap.add_argument("--jobs", type=int, default=256, help="batch: number of jobs")
+    ap.add_argument("--plain-sample", type=int, default=8, help="batch: jobs timed one at a time")
+    ap.add_argument("--autotune", action="store_true", help="batch: measure the workgroup shape first")
+    ap.add_argument("--rate", type=float, default=50.0, help="serve: arrivals per second")
+    ap.add_argument("--duration", type=float, default=60.0, help="serve: seconds of arrivals")
+    ap.add_argument("--arena-gb", type=float, default=16.0, help="serve: device arena")
+    ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--lds", type=int, default=0)
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
     ap.add_argument("--sweeps", type=int, default=0, help="override the workload's sweep count")
     ap.add_argument("--no-cpu", action="store_true")
@@ -145,6 +267,11 @@ def main():
               "(walkers would shard across GPUs with an all-gather of R energies per exchange step)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload in ("batch", "serve"):
+        out = run_batch(args) if args.workload == "batch" else run_serve(args)
+        print(json.dumps(out), flush=True)
+        return
 
     inst = workload(args.workload)
     if args.sweeps:
@@ -160,6 +287,8 @@ def main():
     tr = load_traffic(sha, f"pmc_k_sweep_{args.workload}_{args.precision}.json")
     traffic = None if tr is None else tr["hbm_bytes_per_launch"]
     occupied = min(CUS, inst.R)
+    lds_meas = lds_peak_measured()
+    peak = max(LDS_PEAK, lds_meas or 0.0)
     out = {
         "metric": "spin-flip attempts/sec (all replicas)",
         "value": value,
@@ -184,10 +313,12 @@ def main():
             "bound": "lds",
             "kernel": "k_sweep (persistent, exchange fused)",
             "achieved": achieved / 1e9,
-            "peak": LDS_PEAK / 1e9,
+            "peak": peak / 1e9,
             "unit": "GB/s",
-            "frac": achieved / LDS_PEAK,
-            "frac_occupied_cus": achieved / (LDS_PEAK * occupied / CUS),
+            "frac": achieved / peak,
+            "frac_occupied_cus": achieved / (peak * occupied / CUS),
+            "peak_nominal": LDS_PEAK / 1e9,
+            "peak_measured": None if lds_meas is None else lds_meas / 1e9,
             "traffic": traffic,
             "kernel_ms": kern * 1e3,
             "algorithmic_bytes_per_launch": bytes_,

@@ -9,6 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "ptmi.hip")
 LIB = os.path.join(HERE, "libptmi.so")
+PROBE_SRC = os.path.join(HERE, "csrc", "lds_probe.hip")
+PROBE_LIB = os.path.join(HERE, "libptmi_probe.so")
 ARCH = os.environ.get("PTMI_ARCH", "gfx950")
 
 FLAGS = [
@@ -27,15 +29,20 @@ def hipcc() -> str:
     return exe
 
 
-def build(verbose: bool = False) -> str:
-    """Compile csrc/ptmi.hip (and the headers it includes) into libptmi.so."""
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
-           SRC, "-o", tmp]
+def _compile(src, lib, verbose):
+    tmp = lib + ".tmp%d" % os.getpid()
+    cmd = [hipcc(), *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"), src, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd, cwd=HERE)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile csrc/ptmi.hip (and the headers it includes) into libptmi.so, and
+    the LDS bandwidth probe into libptmi_probe.so."""
+    _compile(SRC, LIB, verbose)
+    _compile(PROBE_SRC, PROBE_LIB, verbose)
     return LIB
 
 

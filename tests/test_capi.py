@@ -58,3 +58,15 @@ def test_host_only_calls():
     assert lib.pt_init(ctypes.byref(ctx), 10, 3, 0.5, ctypes.cast(T, ctypes.c_void_p), 2, 1, None) == pkg.PT_EINVAL
     assert b"ascending" in lib.pt_last_error()
     assert lib.pt_sweep(None, 1) == pkg.PT_EINVAL
+
+
+def test_probe_library_exports():
+    import paper_1308_5426_amd as pkg
+
+    path = os.path.join(os.path.dirname(pkg.LIB_PATH), "libptmi_probe.so")
+    if not os.path.exists(path):
+        pytest.skip("probe library not built")
+    lib = ctypes.CDLL(path)
+    text = open(os.path.join(ROOT, "include", "ptmi_probe.h")).read()
+    for name in re.findall(r"\b(ptmi_[a-z_]+)\s*\(", text):
+        assert hasattr(lib, name)
