@@ -435,8 +435,9 @@ __device__ __forceinline__ void gen_draws(const Inst &P, Walker<F> &W, int w, in
 // by wave 0 alone: the plain sum over the window-start spins in LDS, plus the
 // change brought by each flip already accepted in this window (site ip went
 // from ap to bp, which changes its term by J*(|ip-i|) ([bp=a]-[bp=b]-[ap=a]+[ap=b])).
+// The window's flips are held one per lane in pend_v.
 template <typename F>
-__device__ __forceinline__ double chain_direct_dE(const Walker<F> &W, int L, int i, int a, int b, int np)
+__device__ __forceinline__ double chain_direct_dE(const Walker<F> &W, int L, int i, int a, int b, int np, uint32_t pend_v)
 {
     const int lane = threadIdx.x & (kWave - 1);
     double part = 0.0;
@@ -449,7 +450,7 @@ __device__ __forceinline__ double chain_direct_dE(const Walker<F> &W, int L, int
     }
     double tot = rl_d(wave_sum(part), 0);
     for (int p = 0; p < np; ++p) {
-        const uint32_t pk = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(W.pend[p])));
+        const uint32_t pk = static_cast<uint32_t>(rl_i(static_cast<int>(pend_v), p));
         const int ip = pk & 0xFFFF, ap = (pk >> 16) & 0xFF, bp = pk >> 24;
         const int c = (a == bp) - (b == bp) - (a == ap) + (b == ap);
         if (c != 0) {
@@ -472,11 +473,11 @@ struct ChainRegs {
 // order -- the same operations, in the same order, as the running
 // corrections and the flush, so all three agree bit for bit.
 template <typename F>
-__device__ __forceinline__ F field_now(const Walker<F> &W, int L, int c, int i, int np)
+__device__ __forceinline__ F field_now(const Walker<F> &W, int L, int c, int i, int np, uint32_t pend_v)
 {
     F v = W.h[c * L + i];
     for (int p = 0; p < np; ++p) {
-        const uint32_t pk = W.pend[p];
+        const uint32_t pk = static_cast<uint32_t>(rl_i(static_cast<int>(pend_v), p));
         const int ip = pk & 0xFFFF, ap = (pk >> 16) & 0xFF, bp = pk >> 24;
         if (c == ap || c == bp) {
             int d = i - ip;
@@ -512,14 +513,18 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
     int b = a + kk;
     b -= b >= q ? q : 0;
     F ha = W.h[a * L + i], hb = W.h[b * L + i];
+    int cnt = lane < kQMax ? W.cnt[lane] : 0;  // lane k: sites in state k
+    uint32_t pend_v = 0u;                       // lane p: flip p of this window
     uint64_t live = __ballot(valid);
     int np = 0;
     double Bd = 2.0 * (P.bound_init + static_cast<double>(cr.nupd) * P.bound_unit);
     const double dBd = 2.0 * P.bound_unit;
     int pf_site = -1;  // site whose coupling row pf_jv holds
     F pf_jv = F(0);
+    // the window's first dE before the loop: the loop head then depends only
+    // on values computed in the loop, not on outstanding LDS loads
+    double dE = static_cast<double>(ha) - static_cast<double>(hb);
     while (live) {
-        const double dE = static_cast<double>(ha) - static_cast<double>(hb);
         const double x = beta * dE + lnu;
         const double trig = beta * Bd + kBand + kEvalMargin;
         const uint64_t sure = __ballot(x < -trig) & live;
@@ -534,7 +539,7 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
         double dEf = dE, errf = Bd;
         if (!((sure >> f) & 1ull)) {
             // |x| inside the trigger band: decide with the FP64 direct sum
-            const double d64 = chain_direct_dE(W, L, i_f, a_f, b_f, np);
+            const double d64 = chain_direct_dE(W, L, i_f, a_f, b_f, np, pend_v);
             const double x64 = beta * d64 + rl_d(lnu, f);
             accept = x64 < 0.0;
             dEf = d64;
@@ -548,11 +553,8 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
             }
         }
         if (accept) {
-            if (lane == 0) {
-                W.pend[np] = pk_f;
-                W.cnt[a_f] -= 1;
-                W.cnt[b_f] += 1;
-            }
+            pend_v = lane == np ? pk_f : pend_v;
+            cnt += (lane == b_f) - (lane == a_f);
             if (kF64 && lane == f) {  // FP32 tables take E from the flush's exact sums
                 cr.eL += dEf;
                 cr.errL += errf;
@@ -569,6 +571,20 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
                 d += d < 0 ? L : 0;
                 jv = W.J[d];  // J*(0) = 0 on the flipped site itself
             }
+            const bool later = f < kWave - 1 && ((live >> lane) & 1ull) && lane > f;
+            if (later && i == i_f) {
+                // a later attempt on the flipped site: its two fields are re-derived
+                a = b_f;
+                b = a + kk;
+                b -= b >= q ? q : 0;
+                ha = field_now(W, L, a, i, np, pend_v);
+                hb = field_now(W, L, b, i, np, pend_v);
+            } else {
+                ha = a == a_f ? ha - jv : (a == b_f ? ha + jv : ha);
+                hb = b == a_f ? hb - jv : (b == b_f ? hb + jv : hb);
+            }
+            dE = static_cast<double>(ha) - static_cast<double>(hb);
+            // the next candidate's coupling row, in flight during the next decision
             const uint64_t rest = f == kWave - 1 ? 0ull : cand & (~0ull << (f + 1));
             if (rest) {
                 pf_site = rl_i(i, __builtin_ctzll(rest));
@@ -578,21 +594,11 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
             } else {
                 pf_site = -1;
             }
-            const bool later = f < kWave - 1 && ((live >> lane) & 1ull) && lane > f;
-            if (later && i == i_f) {
-                // a later attempt on the flipped site: its two fields are re-derived
-                a = b_f;
-                b = a + kk;
-                b -= b >= q ? q : 0;
-                ha = field_now(W, L, a, i, np);
-                hb = field_now(W, L, b, i, np);
-            } else {
-                ha = a == a_f ? ha - jv : (a == b_f ? ha + jv : ha);
-                hb = b == a_f ? hb - jv : (b == b_f ? hb + jv : hb);
-            }
         }
         live &= f == kWave - 1 ? 0ull : (~0ull << (f + 1));
     }
+    if (lane < np) W.pend[lane] = pend_v;
+    if (lane < kQMax) W.cnt[lane] = cnt;
     if (lane == 0) W.cs->np[(t0 / kWave) & 1] = np;
 }
 
