@@ -38,11 +38,11 @@ size_t job_bytes(const pt_job_desc &j, int prec)
 
 // Carve of one job inside a workgroup LDS budget: table in LDS if it fits,
 // else in HBM; which kernel variant runs it.
-pt_status job_plan(const pt_job_desc &j, int prec, int budget, LdsPlan *plan, int32_t *variant)
+pt_status job_plan(const pt_job_desc &j, int prec, int budget, int threads, LdsPlan *plan, int32_t *variant)
 {
     const size_t b = static_cast<size_t>(budget);
-    bool in_lds = make_plan(j.L, j.q, j.R, prec, true, true, b, plan);
-    if (!in_lds && !make_plan(j.L, j.q, j.R, prec, true, false, b, plan))
+    bool in_lds = make_plan(j.L, j.q, j.R, prec, true, true, b, threads, plan);
+    if (!in_lds && !make_plan(j.L, j.q, j.R, prec, true, false, b, threads, plan))
         return fail(PT_EINVAL, "job with L = %d, R = %d does not fit an LDS budget of %d B", j.L, j.R, budget);
     int32_t v = 0;
     if (plan->h_in_lds) v |= kVarHLds;
@@ -218,7 +218,7 @@ pt_status pt_batch_create(pt_batch **out, const pt_job_desc *jobs, int32_t njobs
     for (int j = 0; j < njobs; ++j) {
         LdsPlan plan;
         int32_t variant = 0;
-        if ((st = job_plan(jobs[j], b->prec, b->budget, &plan, &variant)) != PT_OK) return bail(st);
+        if ((st = job_plan(jobs[j], b->prec, b->budget, b->threads, &plan, &variant)) != PT_OK) return bail(st);
         b->Tall.insert(b->Tall.end(), jobs[j].T, jobs[j].T + jobs[j].R);
         job_slot(b->slots[j], jobs[j], b->prec, b->ws + b->job_off[j], b->d_T + toff, plan, variant, wbase);
         b->jobs[j].T = nullptr;
@@ -390,7 +390,7 @@ bool server_admit(pt_server *s, std::unique_lock<std::mutex> &lk)
         J.slot = s->published;
         LdsPlan plan;
         int32_t variant = 0;
-        job_plan(J.desc, s->prec, s->budget, &plan, &variant);
+        job_plan(J.desc, s->prec, s->budget, s->threads, &plan, &variant);
         const double *Tdev = s->d_T + static_cast<size_t>(J.slot) * kServerMaxR;
         job_slot(*s->h_slot, J.desc, s->prec, s->mem + off, Tdev, plan, variant, s->wbase);
         std::memcpy(s->h_T, J.T.data(), sizeof(double) * J.desc.R);
@@ -551,7 +551,7 @@ pt_status pt_server_submit(pt_server *s, const pt_job_desc *job, int64_t *id_out
     if (job->R > kServerMaxR) return fail(PT_EINVAL, "server jobs have at most %d replicas", kServerMaxR);
     LdsPlan plan;
     int32_t variant = 0;
-    if ((st = job_plan(*job, s->prec, s->budget, &plan, &variant)) != PT_OK) return st;
+    if ((st = job_plan(*job, s->prec, s->budget, s->threads, &plan, &variant)) != PT_OK) return st;
     const size_t bytes = job_bytes(*job, s->prec);
     if (bytes > s->arena_bytes) return fail(PT_ENOMEM, "job needs %zu B, arena has %zu B", bytes, s->arena_bytes);
     std::lock_guard<std::mutex> g(s->mu);

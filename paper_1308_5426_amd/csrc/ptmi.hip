@@ -78,12 +78,16 @@ int auto_threads(int L)
 int32_t align16(int32_t x) { return (x + 15) & ~15; }
 
 bool make_plan_chunk(int L, int q, int R, int prec, bool fused, bool h_in_lds, size_t lds_max, int chunk,
-                     LdsPlan *p)
+                     int threads, LdsPlan *p)
 {
     const int32_t fb = static_cast<int32_t>(field_bytes(prec));
     const int nblk = (L + kWave - 1) / kWave;
+    // with the table in LDS the coupling row is doubled and padded to the
+    // flush's site slots: J[k] = J*(k mod L) for k < L + passes * threads * kFlushM
+    const int span = threads * kFlushM;
+    p->jlen = h_in_lds ? L + (L + span - 1) / span * span : L;
     int32_t o = 0;
-    p->J = o; o = align16(o + fb * L);
+    p->J = o; o = align16(o + fb * p->jlen);
     p->h_in_lds = h_in_lds ? 1 : 0;
     p->h = o;
     if (h_in_lds) o = align16(o + fb * q * L);
@@ -118,12 +122,12 @@ bool make_plan_chunk(int L, int q, int R, int prec, bool fused, bool h_in_lds, s
 // site masks, spins, counts, reduction scratch, flags, staged draws (the
 // largest chunk of 64..1024 attempts that fits), pending flips, exchange
 // scratch.
-bool make_plan(int L, int q, int R, int prec, bool fused, bool h_in_lds, size_t lds_max, LdsPlan *p)
+bool make_plan(int L, int q, int R, int prec, bool fused, bool h_in_lds, size_t lds_max, int threads, LdsPlan *p)
 {
     const int lmax = std::min(1024, ((L + kWave - 1) / kWave) * kWave);
-    if (make_plan_chunk(L, q, R, prec, fused, h_in_lds, lds_max, lmax, p)) return true;
+    if (make_plan_chunk(L, q, R, prec, fused, h_in_lds, lds_max, lmax, threads, p)) return true;
     for (int chunk = 512; chunk >= kWave; chunk /= 2)
-        if (chunk < lmax && make_plan_chunk(L, q, R, prec, fused, h_in_lds, lds_max, chunk, p)) return true;
+        if (chunk < lmax && make_plan_chunk(L, q, R, prec, fused, h_in_lds, lds_max, chunk, threads, p)) return true;
     return false;
 }
 
@@ -402,18 +406,18 @@ static pt_status init_impl(pt_ctx **out, int32_t L, int32_t q, double sigma, con
         return bail(fail(PT_EDEVICE, "device query failed"));
     // Field table in LDS when it fits (or when asked), else its rows stay in HBM.
     const size_t lmax = static_cast<size_t>(lds_max);
-    bool in_lds = o.placement != PT_PLACE_HBM && make_plan(L, q, R, c->prec, false, true, lmax, &c->plan);
+    bool in_lds = o.placement != PT_PLACE_HBM && make_plan(L, q, R, c->prec, false, true, lmax, c->NT, &c->plan);
     if (o.placement == PT_PLACE_LDS && !in_lds)
         return bail(fail(PT_EINVAL, "field table of %d x %d entries does not fit in %d B of LDS", q, L, lds_max));
-    if (!in_lds && !make_plan(L, q, R, c->prec, false, false, lmax, &c->plan))
+    if (!in_lds && !make_plan(L, q, R, c->prec, false, false, lmax, c->NT, &c->plan))
         return bail(fail(PT_EINVAL, "couplings and spins of L = %d do not fit in %d B of LDS", L, lds_max));
-    bool fused_fits = make_plan(L, q, R, c->prec, true, in_lds, lmax, &c->plan_fused);
+    bool fused_fits = make_plan(L, q, R, c->prec, true, in_lds, lmax, c->NT, &c->plan_fused);
     if (!fused_fits && in_lds && o.placement != PT_PLACE_LDS) {
         // keep the persistent launch possible by moving the table to HBM for it
-        fused_fits = make_plan(L, q, R, c->prec, true, false, lmax, &c->plan_fused);
+        fused_fits = make_plan(L, q, R, c->prec, true, false, lmax, c->NT, &c->plan_fused);
         if (fused_fits) {
             in_lds = false;
-            make_plan(L, q, R, c->prec, false, false, lmax, &c->plan);
+            make_plan(L, q, R, c->prec, false, false, lmax, c->NT, &c->plan);
         }
     }
     c->h_in_lds = in_lds;

@@ -32,7 +32,15 @@ struct LdsPlan {
     int32_t j64_in_lds;   // 1: FP64 couplings resident in LDS
     int32_t h_in_lds;     // 1: field table in LDS; 0: the walker's rows stay in HBM
     int32_t chunk;        // attempts whose draws are staged in LDS at a time (multiple of 64)
+    int32_t jlen;         // entries of the coupling row J: L, or L + flush span when doubled
 };
+
+// Flush geometry: in each pass every wave owns kFlushM blocks of 64
+// consecutive sites; thread (wave v, lane l) holds sites
+// jb + v * 64 * kFlushM + 64 m + l, m < kFlushM.
+constexpr int kFlushM = 4;
+// Flips whose couplings are gathered together before they are applied.
+constexpr int kFlipBatch = 8;
 
 // Scalars of the walker's chain, kept by wave 0 and published through LDS.
 struct ChainState {
@@ -147,10 +155,11 @@ __device__ __forceinline__ void load_walker(const Inst &P, Walker<F> &W, const L
     const uint8_t *ssrc = P.spins + static_cast<size_t>(w) * L;
     double *J64l = plan.j64_in_lds && sizeof(F) != sizeof(double) ? const_cast<double *>(W.J64) : nullptr;
     for (int j = threadIdx.x; j < L; j += blockDim.x) {
-        W.J[j] = Jsrc[j];
         W.sp[j] = ssrc[j];
         if (J64l) J64l[j] = P.J64[j];
     }
+    // J[k] = J*(k mod L): with a doubled row, J*(|j - i|) = J[j - i + L] needs no wrap
+    for (int k = threadIdx.x; k < plan.jlen; k += blockDim.x) W.J[k] = Jsrc[k % L];
     if (plan.h_in_lds)
         for (int e = threadIdx.x; e < q * L; e += blockDim.x) W.h[e] = hsrc[e];
     if (threadIdx.x < kQMax) W.cnt[threadIdx.x] = P.counts[w * kQMax + threadIdx.x];
@@ -435,9 +444,8 @@ __device__ __forceinline__ void gen_draws(const Inst &P, Walker<F> &W, int w, in
 // by wave 0 alone: the plain sum over the window-start spins in LDS, plus the
 // change brought by each flip already accepted in this window (site ip went
 // from ap to bp, which changes its term by J*(|ip-i|) ([bp=a]-[bp=b]-[ap=a]+[ap=b])).
-// The window's flips are held one per lane in pend_v.
 template <typename F>
-__device__ __forceinline__ double chain_direct_dE(const Walker<F> &W, int L, int i, int a, int b, int np, uint32_t pend_v)
+__device__ __forceinline__ double chain_direct_dE(const Walker<F> &W, int L, int i, int a, int b, int np)
 {
     const int lane = threadIdx.x & (kWave - 1);
     double part = 0.0;
@@ -450,7 +458,7 @@ __device__ __forceinline__ double chain_direct_dE(const Walker<F> &W, int L, int
     }
     double tot = rl_d(wave_sum(part), 0);
     for (int p = 0; p < np; ++p) {
-        const uint32_t pk = static_cast<uint32_t>(rl_i(static_cast<int>(pend_v), p));
+        const uint32_t pk = W.pend[p];
         const int ip = pk & 0xFFFF, ap = (pk >> 16) & 0xFF, bp = pk >> 24;
         const int c = (a == bp) - (b == bp) - (a == ap) + (b == ap);
         if (c != 0) {
@@ -473,11 +481,11 @@ struct ChainRegs {
 // order -- the same operations, in the same order, as the running
 // corrections and the flush, so all three agree bit for bit.
 template <typename F>
-__device__ __forceinline__ F field_now(const Walker<F> &W, int L, int c, int i, int np, uint32_t pend_v)
+__device__ __forceinline__ F field_now(const Walker<F> &W, int L, int c, int i, int np)
 {
     F v = W.h[c * L + i];
     for (int p = 0; p < np; ++p) {
-        const uint32_t pk = static_cast<uint32_t>(rl_i(static_cast<int>(pend_v), p));
+        const uint32_t pk = W.pend[p];
         const int ip = pk & 0xFFFF, ap = (pk >> 16) & 0xFF, bp = pk >> 24;
         if (c == ap || c == bp) {
             int d = i - ip;
@@ -488,21 +496,71 @@ __device__ __forceinline__ F field_now(const Walker<F> &W, int L, int c, int i, 
     return v;
 }
 
+__device__ __forceinline__ uint64_t lanes_below(int l) { return l >= kWave ? ~0ull : ((1ull << l) - 1ull); }
+
+// Coupling J*(|i - ip|) of site i to site ip.  D: the row is doubled
+// (J[k] = J*(k mod L) for k < L + span), so no wrap is needed.
+template <bool D, typename F>
+__device__ __forceinline__ F coupling_to(const Walker<F> &W, int L, int i, int ip)
+{
+    if constexpr (D) {
+        return W.J[i + L - ip];
+    } else {
+        int d = i - ip;
+        d += d < 0 ? L : 0;
+        return W.J[d];  // J*(0) = 0 on the flipped site itself
+    }
+}
+
+// Change of the field of state c under a flip ap -> bp, in units of the
+// coupling: -1 if c was the old state, +1 if c is the new one, else 0.  Applied
+// as fma(coef, J, h), which rounds exactly as h - J or h + J (or leaves h).
+template <typename F>
+__device__ __forceinline__ F flip_coef(int c, int ap, int bp)
+{
+    return c == bp ? F(1) : (c == ap ? F(-1) : F(0));  // ap != bp, or both 255 (no flip)
+}
+
+// Flip word of a padding entry: site 0, old = new = 255 (no state), so every
+// coefficient is 0 and the entry changes nothing.
+constexpr uint32_t kNoFlip = 0xFFFF0000u;
+
+// The correction of a later lane's two fields by flip pk: h[a] and h[b] of
+// its site change by coef * J*(|i - ip|).
+template <typename F>
+__device__ __forceinline__ void correct_fields(F &ha, F &hb, bool after, int a, int b, uint32_t pk, F jv)
+{
+    const int ap = static_cast<int>((pk >> 16) & 0xFFu), bp = static_cast<int>(pk >> 24);
+    const F ca = after ? flip_coef<F>(a, ap, bp) : F(0);
+    const F cb = after ? flip_coef<F>(b, ap, bp) : F(0);
+    ha = fma(ca, jv, ha);
+    hb = fma(cb, jv, hb);
+}
+
 // Wave 0: the chain through attempts [t0, t0 + 64) (lanes past `cend` idle).
 // Each lane keeps only the two fields its attempt needs, ha = h[a][i] and
-// hb = h[b][i], and corrects them after every accepted flip.  Two ballots
-// split the candidates into sure accepts (x < -trig) and near-threshold ones
-// (|x| <= trig, FP64 recheck); the first candidate is taken.  The coupling
-// row of the next candidate is fetched while the current flip is applied,
-// which hides the LDS latency whenever that candidate is the next accept.
-// Energy increments stay in the accepting lane (eL, errL) and are summed at
-// the end of the sweep.
-template <typename F>
+// hb = h[b][i].  The sequential chain is resolved by guess and check: every
+// attempt that is a sure accept under the current fields is guessed to be
+// accepted; the guessed flips are applied, in order, to the fields of the
+// later lanes (couplings gathered kFlipBatch flips at a time); the guess
+// stops at the first later attempt on a site a guessed flip changed, whose
+// state the guess cannot know.  Each lane then re-decides with exactly the
+// guessed flips before it, and its own bound.  Up to the first lane whose
+// decision differs from the guess, every lane saw precisely the flips the
+// sequential chain would have accepted before it, so that prefix is committed;
+// the differing lane is decided (near-threshold ones by the FP64 direct sum),
+// and the later lanes' fields are rebuilt from the committed flips.  The
+// commit is the same arithmetic, in the same order, as taking the accepts one
+// by one.  Energy increments stay in the accepting lane (eL, errL) and are
+// summed at the end of the sweep.
+template <typename F, bool D>
 __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w, int64_t n, double beta, int t0,
                                              int c0, int cend, ChainRegs &cr)
 {
     constexpr bool kF64 = sizeof(F) == sizeof(double);
+    constexpr int B = kFlipBatch;
     const int L = P.L, q = P.q, lane = threadIdx.x & (kWave - 1);
+    const uint64_t mine_below = lanes_below(lane);
     const int ta = t0 + lane;
     const bool valid = ta < cend;
     const uint32_t dr = valid ? W.draw[ta - c0] : 0u;
@@ -513,126 +571,182 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
     int b = a + kk;
     b -= b >= q ? q : 0;
     F ha = W.h[a * L + i], hb = W.h[b * L + i];
-    int cnt = lane < kQMax ? W.cnt[lane] : 0;  // lane k: sites in state k
-    uint32_t pend_v = 0u;                       // lane p: flip p of this window
     uint64_t live = __ballot(valid);
     int np = 0;
     double Bd = 2.0 * (P.bound_init + static_cast<double>(cr.nupd) * P.bound_unit);
     const double dBd = 2.0 * P.bound_unit;
-    int pf_site = -1;  // site whose coupling row pf_jv holds
-    F pf_jv = F(0);
-    // the window's first dE before the loop: the loop head then depends only
-    // on values computed in the loop, not on outstanding LDS loads
-    double dE = static_cast<double>(ha) - static_cast<double>(hb);
+    const double tfix = kBand + kEvalMargin;
     while (live) {
-        const double x = beta * dE + lnu;
-        const double trig = beta * Bd + kBand + kEvalMargin;
-        const uint64_t sure = __ballot(x < -trig) & live;
-        const uint64_t cand = (__ballot(x < trig) & live) | sure;
-        if (cand == 0) break;
-        const int f = __builtin_ctzll(cand);
         const uint32_t pk = static_cast<uint32_t>(i) | (static_cast<uint32_t>(a) << 16) | (static_cast<uint32_t>(b) << 24);
-        const uint32_t pk_f = static_cast<uint32_t>(rl_i(static_cast<int>(pk), f));
-        const int i_f = static_cast<int>(pk_f & 0xFFFFu), a_f = static_cast<int>((pk_f >> 16) & 0xFFu),
-                  b_f = static_cast<int>(pk_f >> 24);
-        bool accept = true;
-        double dEf = dE, errf = Bd;
-        if (!((sure >> f) & 1ull)) {
-            // |x| inside the trigger band: decide with the FP64 direct sum
-            const double d64 = chain_direct_dE(W, L, i_f, a_f, b_f, np, pend_v);
-            const double x64 = beta * d64 + rl_d(lnu, f);
-            accept = x64 < 0.0;
-            dEf = d64;
-            errf = 0.0;
-            if (lane == 0) {
-                atomicAdd(&P.ctr[kCtrRecheck], 1ull);
-                if (fabs(x64) <= kBand) {
-                    atomicAdd(&P.ctr[kCtrBandedMet], 1ull);
-                    log_event(P, 0, w, n, t0 + f, accept ? 1 : 0, x64);
+        // guess: the sure accepts under the current fields
+        double dE = static_cast<double>(ha) - static_cast<double>(hb);
+        uint64_t S = __ballot(beta * dE + lnu < -(beta * Bd + tfix)) & live;
+        const F ha0 = ha, hb0 = hb;
+        int hz = kWave;        // first lane on a site changed by a guessed flip before it
+        int sfl = -1, sb = 0;  // that flip's lane and new state, for this lane
+        uint64_t rem = S;
+        bool go = true;
+        while (rem && go) {
+            int pb[B];
+            uint32_t pkb[B];
+            F jb[B];
+#pragma unroll
+            for (int e = 0; e < B; ++e) {  // padding entries: lane 64, no flip
+                pb[e] = rem ? static_cast<int>(__builtin_ctzll(rem)) : kWave;
+                rem &= rem - 1ull;
+                pkb[e] = pb[e] < kWave ? static_cast<uint32_t>(rl_i(static_cast<int>(pk), pb[e])) : kNoFlip;
+                jb[e] = coupling_to<D>(W, L, i, static_cast<int>(pkb[e] & 0xFFFFu));
+            }
+            // applied without branches (a skipped entry corrects no lane), so
+            // the batch's gathers stay in flight together
+#pragma unroll
+            for (int e = 0; e < B; ++e) {
+                go = go && pb[e] < hz;
+                const bool after = go && lane > pb[e];
+                const bool same = valid && after && i == static_cast<int>(pkb[e] & 0xFFFFu);
+                const uint64_t st = __ballot(same);
+                hz = st ? min(hz, static_cast<int>(__builtin_ctzll(st))) : hz;
+                sfl = same ? pb[e] : sfl;
+                sb = same ? static_cast<int>(pkb[e] >> 24) : sb;
+                correct_fields(ha, hb, after, a, b, pkb[e], jb[e]);
+            }
+        }
+        S &= lanes_below(hz);
+        // check: each lane decides with the guessed flips before it
+        dE = static_cast<double>(ha) - static_cast<double>(hb);
+        const double x = beta * dE + lnu;
+        const int r = __popcll(S & mine_below);
+        const double Bdl = Bd + static_cast<double>(r) * dBd;
+        const double trig = beta * Bdl + tfix;
+        const bool inS = (S >> lane) & 1ull;
+        const bool sure = x < -trig, rej = x > trig;
+        const uint64_t V = __ballot(inS ? !sure : !rej) & live & lanes_below(hz);
+        const int m = V ? static_cast<int>(__builtin_ctzll(V)) : hz;
+        const uint64_t C = S & lanes_below(m);
+        if ((C >> lane) & 1ull) {
+            W.pend[np + r] = pk;
+            atomicAdd(&W.cnt[a], -1);
+            atomicAdd(&W.cnt[b], 1);
+            if (kF64) {  // FP32 tables take E from the flush's exact sums
+                cr.eL += dE;
+                cr.errL += Bdl;
+            }
+        }
+        const int nc = __popcll(C);
+        np += nc;
+        cr.nupd += nc;
+        cr.nacc += nc;
+        Bd += static_cast<double>(nc) * dBd;
+        bool stale = sfl >= 0 && sfl < m;  // a committed flip changed this lane's site
+        if (V) {
+            // lane m holds exactly the committed flips: decide it
+            const uint32_t pk_m = static_cast<uint32_t>(rl_i(static_cast<int>(pk), m));
+            const int i_m = static_cast<int>(pk_m & 0xFFFFu), a_m = static_cast<int>((pk_m >> 16) & 0xFFu),
+                      b_m = static_cast<int>(pk_m >> 24);
+            bool accept = (__ballot(sure) >> m) & 1ull;
+            double dEm = rl_d(dE, m), errm = Bd;
+            if (!accept && !((__ballot(rej) >> m) & 1ull)) {
+                // |x| inside the trigger band: decide with the FP64 direct sum
+                const double d64 = chain_direct_dE(W, L, i_m, a_m, b_m, np);
+                const double x64 = beta * d64 + rl_d(lnu, m);
+                accept = x64 < 0.0;
+                dEm = d64;
+                errm = 0.0;
+                if (lane == 0) {
+                    atomicAdd(&P.ctr[kCtrRecheck], 1ull);
+                    if (fabs(x64) <= kBand) {
+                        atomicAdd(&P.ctr[kCtrBandedMet], 1ull);
+                        log_event(P, 0, w, n, t0 + m, accept ? 1 : 0, x64);
+                    }
                 }
             }
+            // rebuild the later lanes' fields from the committed flips
+            ha = ha0;
+            hb = hb0;
+            uint64_t cm = C;
+            while (cm) {
+                int pb[B];
+                uint32_t pkb[B];
+                F jb[B];
+#pragma unroll
+                for (int e = 0; e < B; ++e) {
+                    pb[e] = cm ? static_cast<int>(__builtin_ctzll(cm)) : kWave;
+                    cm &= cm - 1ull;
+                    pkb[e] = pb[e] < kWave ? static_cast<uint32_t>(rl_i(static_cast<int>(pk), pb[e])) : kNoFlip;
+                    jb[e] = coupling_to<D>(W, L, i, static_cast<int>(pkb[e] & 0xFFFFu));
+                }
+#pragma unroll
+                for (int e = 0; e < B; ++e) correct_fields(ha, hb, lane > pb[e], a, b, pkb[e], jb[e]);
+            }
+            if (accept) {
+                if (lane == m) {
+                    W.pend[np] = pk_m;
+                    atomicAdd(&W.cnt[a_m], -1);
+                    atomicAdd(&W.cnt[b_m], 1);
+                    if (kF64) {
+                        cr.eL += dEm;
+                        cr.errL += errm;
+                    }
+                }
+                ++np;
+                ++cr.nupd;
+                ++cr.nacc;
+                Bd += dBd;
+                correct_fields(ha, hb, lane > m, a, b, pk_m, coupling_to<D>(W, L, i, i_m));
+                if (lane > m && i == i_m) {
+                    stale = true;
+                    sb = b_m;
+                }
+            }
+            live &= ~lanes_below(m + 1);
+        } else {
+            live &= ~lanes_below(hz);
         }
-        if (accept) {
-            pend_v = lane == np ? pk_f : pend_v;
-            cnt += (lane == b_f) - (lane == a_f);
-            if (kF64 && lane == f) {  // FP32 tables take E from the flush's exact sums
-                cr.eL += dEf;
-                cr.errL += errf;
-            }
-            ++np;
-            ++cr.nupd;
-            ++cr.nacc;
-            Bd += dBd;
-            F jv;
-            if (i_f == pf_site) {
-                jv = pf_jv;
-            } else {
-                int d = i - i_f;
-                d += d < 0 ? L : 0;
-                jv = W.J[d];  // J*(0) = 0 on the flipped site itself
-            }
-            const bool later = f < kWave - 1 && ((live >> lane) & 1ull) && lane > f;
-            if (later && i == i_f) {
-                // a later attempt on the flipped site: its two fields are re-derived
-                a = b_f;
-                b = a + kk;
-                b -= b >= q ? q : 0;
-                ha = field_now(W, L, a, i, np, pend_v);
-                hb = field_now(W, L, b, i, np, pend_v);
-            } else {
-                ha = a == a_f ? ha - jv : (a == b_f ? ha + jv : ha);
-                hb = b == a_f ? hb - jv : (b == b_f ? hb + jv : hb);
-            }
-            dE = static_cast<double>(ha) - static_cast<double>(hb);
-            // the next candidate's coupling row, in flight during the next decision
-            const uint64_t rest = f == kWave - 1 ? 0ull : cand & (~0ull << (f + 1));
-            if (rest) {
-                pf_site = rl_i(i, __builtin_ctzll(rest));
-                int d = i - pf_site;
-                d += d < 0 ? L : 0;
-                pf_jv = W.J[d];
-            } else {
-                pf_site = -1;
-            }
+        // later lanes on a flipped site: new current state, fields re-derived
+        if (stale && ((live >> lane) & 1ull)) {
+            a = sb;
+            b = a + kk;
+            b -= b >= q ? q : 0;
+            ha = field_now(W, L, a, i, np);
+            hb = field_now(W, L, b, i, np);
         }
-        live &= f == kWave - 1 ? 0ull : (~0ull << (f + 1));
     }
-    if (lane < np) W.pend[lane] = pend_v;
-    if (lane < kQMax) W.cnt[lane] = cnt;
     if (lane == 0) W.cs->np[(t0 / kWave) & 1] = np;
 }
 
 // Whole workgroup: apply the window's np flips to the table.  Each thread
-// owns up to 4 sites per pass and applies the flips to them in order, so no
+// owns kFlushM sites per pass and applies the flips to them in order, so no
 // barrier is needed between flips.  QT > 0: the sites' q <= QT fields sit in
-// registers for the pass (one table read and write per field); QT = 0: the
-// two rows a flip touches are updated in LDS directly (fewer registers, for
-// larger q).  The arithmetic per field is the same sequence either way.  The
-// flip list is read once into a register (lane p holds flip p) and each
-// flip's couplings are loaded while the previous flip is applied.
-// With an FP32 table the same pass forms the exact FP64 energy change of
-// every flip, sum_j J*(|j-i|)[delta(a, s_j) - delta(b, s_j)], over the spins
-// as they were just before it (partial sums per thread).
-template <typename F, int QT>
+// registers for the pass (one table read and write per field) and every flip
+// is applied to all of them as fma(coef, J, h) with a wave-uniform
+// coefficient (-1, 0 or +1), which rounds exactly as h - J or h + J; QT = 0:
+// the two rows a flip touches are updated in LDS directly (fewer registers,
+// for larger q).  The couplings of kFlipBatch flips are gathered before they
+// are applied; with a doubled coupling row (D) one address serves a flip's
+// kFlushM gathers.  With an FP32 table the same pass forms the exact FP64
+// energy change of every flip, sum_j J*(|j-i|)[delta(a, s_j) - delta(b, s_j)],
+// over the spins as they were just before it (partial sums per thread).
+template <typename F, int QT, bool D>
 __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np, double &part)
 {
-    constexpr int NJB = 4;
+    constexpr int M = kFlushM, B = kFlipBatch;
     constexpr bool kF32 = sizeof(F) == sizeof(float);
     const int L = P.L, q = P.q, tid = threadIdx.x, NT = blockDim.x, lane = tid & (kWave - 1);
-    const uint32_t pv = lane < np ? W.pend[lane] : 0u;
+    const uint32_t pv = lane < np ? W.pend[lane] : kNoFlip;
     if (!kF32 && tid == 0)
         for (int p = 0; p < np; ++p) {
             const uint32_t pk = static_cast<uint32_t>(rl_i(static_cast<int>(pv), p));
             W.sp[pk & 0xFFFFu] = static_cast<uint8_t>(pk >> 24);
         }
-    for (int jb = 0; jb < L; jb += NT * NJB) {
-        int jm[NJB];
-        bool ok[NJB];
-        F hr[QT > 0 ? QT : 1][NJB];
-        int sr[NJB];
+    for (int jb = (tid / kWave) * kWave * M; jb < L; jb += NT * M) {
+        const int j0 = jb + lane;
+        int jm[M];
+        bool ok[M];
+        F hr[QT > 0 ? QT : 1][M];
+        int sr[M];
 #pragma unroll
-        for (int m = 0; m < NJB; ++m) {
-            const int j = jb + m * NT + tid;
+        for (int m = 0; m < M; ++m) {
+            const int j = j0 + m * kWave;
             ok[m] = j < L;
             jm[m] = ok[m] ? j : 0;
             sr[m] = (kF32 && ok[m]) ? W.sp[j] : -1;
@@ -640,89 +754,76 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
 #pragma unroll
         for (int c = 0; c < QT; ++c)
 #pragma unroll
-            for (int m = 0; m < NJB; ++m) hr[c][m] = (c < q && ok[m]) ? W.h[c * L + jm[m]] : F(0);
+            for (int m = 0; m < M; ++m) hr[c][m] = (c < q && ok[m]) ? W.h[c * L + jm[m]] : F(0);
         (void)hr;
-        // couplings of flip 0
-        uint32_t pk = static_cast<uint32_t>(rl_i(static_cast<int>(pv), 0));
-        F jv[NJB];
-        double j64[NJB];
-        int dd[NJB];
+        const F *Jrow = W.J + (j0 + L);  // D: coupling of site j0 + 64 m to site ip is Jrow[64 m - ip]
+        for (int p0 = 0; p0 < np; p0 += B) {
+            uint32_t pkb[B];
+            F g[B][M];
+            double g64[B][M];
 #pragma unroll
-        for (int m = 0; m < NJB; ++m) {
-            int d = jm[m] - static_cast<int>(pk & 0xFFFFu);
-            d += d < 0 ? L : 0;
-            dd[m] = d;
-            jv[m] = W.J[d];
-            j64[m] = kF32 ? W.J64[d] : 0.0;
-        }
-        for (int p = 0; p < np; ++p) {
-            const int ip = static_cast<int>(pk & 0xFFFFu), ap = static_cast<int>((pk >> 16) & 0xFFu),
-                      bp = static_cast<int>(pk >> 24);
-            F cj[NJB];
-            double c64[NJB];
+            for (int e = 0; e < B; ++e) {
+                // p0 + e <= 63; lanes past np hold the no-flip word
+                pkb[e] = static_cast<uint32_t>(rl_i(static_cast<int>(pv), p0 + e));
+                const int ip = static_cast<int>(pkb[e] & 0xFFFFu);
 #pragma unroll
-            for (int m = 0; m < NJB; ++m) {
-                cj[m] = jv[m];
-                c64[m] = j64[m];
-            }
-            if (p + 1 < np) {  // next flip's couplings in flight while this one is applied
-                pk = static_cast<uint32_t>(rl_i(static_cast<int>(pv), p + 1));
-#pragma unroll
-                for (int m = 0; m < NJB; ++m) {
-                    int d = jm[m] - static_cast<int>(pk & 0xFFFFu);
+                for (int m = 0; m < M; ++m) {
+                    int d = jm[m] - ip;
                     d += d < 0 ? L : 0;
-                    dd[m] = d;
-                    jv[m] = W.J[d];
-                    j64[m] = kF32 ? W.J64[d] : 0.0;
+                    if constexpr (D)
+                        g[e][m] = Jrow[m * kWave - ip];
+                    else
+                        g[e][m] = W.J[d];
+                    g64[e][m] = kF32 ? W.J64[d] : 0.0;
                 }
             }
-            if constexpr (QT > 0) {
 #pragma unroll
-                for (int c = 0; c < QT; ++c) {
-                    if (c == ap) {
+            for (int e = 0; e < B; ++e) {
+                const bool real = p0 + e < np;
+                const int ip = static_cast<int>(pkb[e] & 0xFFFFu), ap = static_cast<int>((pkb[e] >> 16) & 0xFFu),
+                          bp = static_cast<int>(pkb[e] >> 24);
+                if constexpr (QT > 0) {  // no branch: padding entries have all coefficients 0
 #pragma unroll
-                        for (int m = 0; m < NJB; ++m) hr[c][m] -= cj[m];
+                    for (int c = 0; c < QT; ++c) {
+                        const F k = flip_coef<F>(c, ap, bp);
+#pragma unroll
+                        for (int m = 0; m < M; ++m) hr[c][m] = fma(k, g[e][m], hr[c][m]);
                     }
-                    if (c == bp) {
+                } else if (real) {
+                    F *ra = W.h + ap * L, *rb = W.h + bp * L;
 #pragma unroll
-                        for (int m = 0; m < NJB; ++m) hr[c][m] += cj[m];
-                    }
+                    for (int m = 0; m < M; ++m)
+                        if (ok[m]) {
+                            ra[jm[m]] -= g[e][m];
+                            rb[jm[m]] += g[e][m];
+                        }
                 }
-            } else {
-                F *ra = W.h + ap * L, *rb = W.h + bp * L;
+                if (kF32) {
 #pragma unroll
-                for (int m = 0; m < NJB; ++m)
-                    if (ok[m]) {
-                        ra[jm[m]] -= cj[m];
-                        rb[jm[m]] += cj[m];
+                    for (int m = 0; m < M; ++m) {
+                        const int s = sr[m];
+                        part += s == ap ? g64[e][m] : (s == bp ? -g64[e][m] : 0.0);
+                        sr[m] = (real && ok[m] && jm[m] == ip) ? bp : s;
                     }
-            }
-            if (kF32) {
-#pragma unroll
-                for (int m = 0; m < NJB; ++m) {
-                    const int s = sr[m];
-                    part += s == ap ? c64[m] : (s == bp ? -c64[m] : 0.0);
-                    sr[m] = (ok[m] && jm[m] == ip) ? bp : s;
                 }
             }
         }
-        (void)dd;
 #pragma unroll
         for (int c = 0; c < QT; ++c)
 #pragma unroll
-            for (int m = 0; m < NJB; ++m)
+            for (int m = 0; m < M; ++m)
                 if (c < q && ok[m]) W.h[c * L + jm[m]] = hr[c][m];
         if (kF32) {
 #pragma unroll
-            for (int m = 0; m < NJB; ++m)
+            for (int m = 0; m < M; ++m)
                 if (ok[m]) W.sp[jm[m]] = static_cast<uint8_t>(sr[m]);
         }
     }
 }
 
 // One sweep of walker w at sweep index n.  Returns this thread's part of the
-// exact energy change (FP32 table; zero otherwise).
-template <typename F, int QT>
+// exact energy change (FP32 table; zero otherwise).  D: doubled coupling row.
+template <typename F, int QT, bool D>
 __device__ __forceinline__ double sweep_walker(const Inst &P, Walker<F> &W, int w, int64_t n, double beta, ChainRegs &cr)
 {
     const int L = P.L, wave = threadIdx.x / kWave;
@@ -732,11 +833,11 @@ __device__ __forceinline__ double sweep_walker(const Inst &P, Walker<F> &W, int 
         gen_draws<F>(P, W, w, n, c0, cend - c0);
         __syncthreads();
         for (int t0 = c0; t0 < cend; t0 += kWave) {
-            if (wave == 0) chain_window<F>(P, W, w, n, beta, t0, c0, cend, cr);
+            if (wave == 0) chain_window<F, D>(P, W, w, n, beta, t0, c0, cend, cr);
             __syncthreads();
             const int np = W.cs->np[(t0 / kWave) & 1];
             if (np > 0) {
-                flush_window<F, QT>(P, W, np, part);
+                flush_window<F, QT, D>(P, W, np, part);
                 __syncthreads();
             }
         }
@@ -810,7 +911,7 @@ __device__ __forceinline__ bool run_walker(const Inst &P, const LdsPlan &plan, u
         const int slot = __hip_atomic_load(&P.slot_of[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const double beta = P.beta[slot];
         cr.nacc = 0;
-        const double part = sweep_walker<F, QT>(P, W, w, n, beta, cr);
+        const double part = sweep_walker<F, QT, HLDS>(P, W, w, n, beta, cr);
         // energy change of the sweep: the flush's exact sums (FP32 table) or
         // the accepted flips' dE held by the chain lanes (FP64 table)
         cr.E += block_sum(part + cr.eL, W.red);

@@ -83,17 +83,26 @@ def test_batch_equals_single_instance(pkg):
             dict(L=64, q=5, sigma=0.3, T=geometric_ladder(0.2, 2.0, 5), seed=78, sweeps=50, exchange_every=2, init=1)]
     b = pkg.Batch(jobs)
     b.run()
+    nt = b.shape()["threads"]
     for j, job in enumerate(jobs):
-        sim = pkg.Simulation(job["L"], job["q"], job["sigma"], job["T"], job["seed"], init=job["init"])
-        sim.run(job["sweeps"], job["exchange_every"])
-        s1, p1 = sim.spins()
-        s2, p2 = b.spins(j)
-        np.testing.assert_array_equal(s1, s2)
-        np.testing.assert_array_equal(p1, p2)
-        o1, o2 = sim.observables(), b.observables(j)
-        for k in ("flip_acc", "xchg_acc", "sumE", "sumM2"):
-            np.testing.assert_array_equal(o1[k], o2[k])
-        sim.close()
+        # same workgroup width: the FP64 energy reductions then run in the same order
+        for threads, exact in ((nt, True), (0, False)):
+            sim = pkg.Simulation(job["L"], job["q"], job["sigma"], job["T"], job["seed"], init=job["init"],
+                                 threads=threads)
+            sim.run(job["sweeps"], job["exchange_every"])
+            s1, p1 = sim.spins()
+            s2, p2 = b.spins(j)
+            np.testing.assert_array_equal(s1, s2)
+            np.testing.assert_array_equal(p1, p2)
+            o1, o2 = sim.observables(), b.observables(j)
+            for k in ("flip_acc", "flip_att", "xchg_acc", "sumM2"):
+                np.testing.assert_array_equal(o1[k], o2[k])
+            if exact:
+                np.testing.assert_array_equal(o1["sumE"], o2["sumE"])
+            else:
+                # another width sums the per-thread FP64 partials in another order
+                np.testing.assert_allclose(o1["sumE"], o2["sumE"], rtol=job["L"] ** 2 * 2.0 ** -52)
+            sim.close()
     b.close()
 
 
