@@ -14,6 +14,9 @@ constexpr int kWave = 64;
 constexpr int kQMax = 16;
 constexpr double kBand = 1e-9;
 
+// Lanes of the wave where p holds; the compare feeding it stays a lane mask.
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw; SC'11): ten rounds of two
 // 32x32->64 multiplies with the key advanced by the Weyl constants.

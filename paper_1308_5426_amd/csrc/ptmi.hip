@@ -114,6 +114,15 @@ bool make_plan_chunk(int L, int q, int R, int prec, bool fused, bool h_in_lds, s
         p->J64 = 0;
         p->j64_in_lds = 0;
     }
+    const int nw = threads / kWave;
+    p->xpart = o; o = align16(o + 2 * nw * kWave * 8);
+    // optional: the chain's first-guessed-flip tables (4 B per site and wave)
+    if (static_cast<size_t>(o) + 4u * L * nw <= lds_max) {
+        p->sfirst = o;
+        o = align16(o + 4 * L * nw);
+    } else {
+        p->sfirst = -1;
+    }
     p->total = o;
     return static_cast<size_t>(o) <= lds_max;
 }

@@ -33,6 +33,8 @@ struct LdsPlan {
     int32_t h_in_lds;     // 1: field table in LDS; 0: the walker's rows stay in HBM
     int32_t chunk;        // attempts whose draws are staged in LDS at a time (multiple of 64)
     int32_t jlen;         // entries of the coupling row J: L, or L + flush span when doubled
+    int32_t sfirst;       // [waves][L] u32 first-guessed-flip tables, or -1 when they do not fit
+    int32_t xpart;        // [2][waves][64] FP64 partial corrections exchanged between waves
 };
 
 // Flush geometry: in each pass every wave owns kFlushM blocks of 64
@@ -71,7 +73,9 @@ struct Walker {
     int32_t *misc;      // [8]
     uint32_t *draw;     // [chunk] site | offset << 16
     double *dlnu;       // [chunk] ln u
-    uint32_t *pend;     // [64] flips accepted in the current window: i | a << 16 | b << 24
+    uint32_t *pend;     // [64] flip words of the flips accepted in the current window
+    uint32_t *sfirst;   // [waves][L] per site: first lane of the current guess flipping it (64: none), or null
+    double *xpart;      // [2][waves][64] partial corrections of the split passes
     ChainState *cs;
     int32_t chunk;
 };
@@ -101,6 +105,8 @@ __device__ __forceinline__ Walker<F> carve(unsigned char *lds, const LdsPlan &p,
     W.dlnu = reinterpret_cast<double *>(lds + p.dlnu);
     W.pend = reinterpret_cast<uint32_t *>(lds + p.pend);
     W.cs = reinterpret_cast<ChainState *>(lds + p.cs);
+    W.sfirst = p.sfirst >= 0 ? reinterpret_cast<uint32_t *>(lds + p.sfirst) : nullptr;
+    W.xpart = reinterpret_cast<double *>(lds + p.xpart);
     W.chunk = p.chunk;
     return W;
 }
@@ -158,6 +164,8 @@ __device__ __forceinline__ void load_walker(const Inst &P, Walker<F> &W, const L
         W.sp[j] = ssrc[j];
         if (J64l) J64l[j] = P.J64[j];
     }
+    if (W.sfirst)
+        for (int k = threadIdx.x; k < (blockDim.x / kWave) * L; k += blockDim.x) W.sfirst[k] = kWave;
     // J[k] = J*(k mod L): with a doubled row, J*(|j - i|) = J[j - i + L] needs no wrap
     for (int k = threadIdx.x; k < plan.jlen; k += blockDim.x) W.J[k] = Jsrc[k % L];
     if (plan.h_in_lds)
@@ -194,7 +202,7 @@ __device__ __forceinline__ double refresh_fields(const Inst &P, Walker<F> &W)
         const int j = blk * kWave + lane;
         const int s = j < L ? W.sp[j] : -1;
         for (int k = 0; k < q; ++k) {
-            const uint64_t m = __ballot(s == k);
+            const uint64_t m = ballot(s == k);
             if (lane == 0) W.masks[k * nblk + blk] = m;
         }
     }
@@ -441,11 +449,10 @@ __device__ __forceinline__ void gen_draws(const Inst &P, Walker<F> &W, int w, in
 }
 
 // FP64 energy difference of flipping site i from a to b in the current state,
-// by wave 0 alone: the plain sum over the window-start spins in LDS, plus the
-// change brought by each flip already accepted in this window (site ip went
-// from ap to bp, which changes its term by J*(|ip-i|) ([bp=a]-[bp=b]-[ap=a]+[ap=b])).
+// by wave 0 alone: the plain sum over the spins in LDS, which the chain keeps
+// current (each committed flip writes its spin at once).
 template <typename F>
-__device__ __forceinline__ double chain_direct_dE(const Walker<F> &W, int L, int i, int a, int b, int np)
+__device__ __forceinline__ double chain_direct_dE(const Walker<F> &W, int L, int i, int a, int b)
 {
     const int lane = threadIdx.x & (kWave - 1);
     double part = 0.0;
@@ -456,18 +463,7 @@ __device__ __forceinline__ double chain_direct_dE(const Walker<F> &W, int L, int
         const double jv = W.J64[d];
         part += s == a ? jv : (s == b ? -jv : 0.0);
     }
-    double tot = rl_d(wave_sum(part), 0);
-    for (int p = 0; p < np; ++p) {
-        const uint32_t pk = W.pend[p];
-        const int ip = pk & 0xFFFF, ap = (pk >> 16) & 0xFF, bp = pk >> 24;
-        const int c = (a == bp) - (b == bp) - (a == ap) + (b == ap);
-        if (c != 0) {
-            int d = ip - i;
-            d += d < 0 ? L : 0;
-            tot += static_cast<double>(c) * W.J64[d];
-        }
-    }
-    return tot;
+    return rl_d(wave_sum(part), 0);
 }
 
 struct ChainRegs {
@@ -476,27 +472,12 @@ struct ChainRegs {
     double eL, errL;    // energy increments held by the accepting lanes (wave 0)
 };
 
-// Field of state c at site i as the chain sees it: the table entry (window
-// start) plus the flips 0..np-1 already accepted in this window, applied in
-// order -- the same operations, in the same order, as the running
-// corrections and the flush, so all three agree bit for bit.
-template <typename F>
-__device__ __forceinline__ F field_now(const Walker<F> &W, int L, int c, int i, int np)
-{
-    F v = W.h[c * L + i];
-    for (int p = 0; p < np; ++p) {
-        const uint32_t pk = W.pend[p];
-        const int ip = pk & 0xFFFF, ap = (pk >> 16) & 0xFF, bp = pk >> 24;
-        if (c == ap || c == bp) {
-            int d = i - ip;
-            d += d < 0 ? L : 0;
-            v = c == ap ? v - W.J[d] : v + W.J[d];
-        }
-    }
-    return v;
-}
-
 __device__ __forceinline__ uint64_t lanes_below(int l) { return l >= kWave ? ~0ull : ((1ull << l) - 1ull); }
+
+template <bool D, typename F>
+__device__ __forceinline__ F coupling_to(const Walker<F> &W, int L, int i, int ip);
+template <typename F>
+__device__ __forceinline__ F flip_coef(int c, int ap, int bp);
 
 // Coupling J*(|i - ip|) of site i to site ip.  D: the row is doubled
 // (J[k] = J*(k mod L) for k < L + span), so no wrap is needed.
@@ -518,48 +499,180 @@ __device__ __forceinline__ F coupling_to(const Walker<F> &W, int L, int i, int i
 template <typename F>
 __device__ __forceinline__ F flip_coef(int c, int ap, int bp)
 {
-    return c == bp ? F(1) : (c == ap ? F(-1) : F(0));  // ap != bp, or both 255 (no flip)
+    // +1 for the new state, -1 for the old one; 0 otherwise, and for ap == bp (no flip)
+    return c == bp ? (c == ap ? F(0) : F(1)) : (c == ap ? F(-1) : F(0));
 }
 
-// Flip word of a padding entry: site 0, old = new = 255 (no state), so every
-// coefficient is 0 and the entry changes nothing.
-constexpr uint32_t kNoFlip = 0xFFFF0000u;
-
-// The correction of a later lane's two fields by flip pk: h[a] and h[b] of
-// its site change by coef * J*(|i - ip|).
-template <typename F>
-__device__ __forceinline__ void correct_fields(F &ha, F &hb, bool after, int a, int b, uint32_t pk, F jv)
+// Flip word: site (bits 0-15), old state (16-19), new state (20-23), and the
+// chain's lane of the attempt in its window (24-29).
+__device__ __forceinline__ uint32_t flip_word(int i, int a, int b, int lane)
 {
-    const int ap = static_cast<int>((pk >> 16) & 0xFFu), bp = static_cast<int>(pk >> 24);
-    const F ca = after ? flip_coef<F>(a, ap, bp) : F(0);
-    const F cb = after ? flip_coef<F>(b, ap, bp) : F(0);
-    ha = fma(ca, jv, ha);
-    hb = fma(cb, jv, hb);
+    return static_cast<uint32_t>(i) | (static_cast<uint32_t>(a) << 16) | (static_cast<uint32_t>(b) << 20) |
+           (static_cast<uint32_t>(lane) << 24);
+}
+__device__ __forceinline__ int fw_site(uint32_t w) { return static_cast<int>(w & 0xFFFFu); }
+__device__ __forceinline__ int fw_old(uint32_t w) { return static_cast<int>((w >> 16) & 0xFu); }
+__device__ __forceinline__ int fw_new(uint32_t w) { return static_cast<int>((w >> 20) & 0xFu); }
+__device__ __forceinline__ int fw_lane(uint32_t w) { return static_cast<int>((w >> 24) & 0x3Fu); }
+// Padding entry: site 0, state 0 -> 0 (every coefficient 0), lane 63 (no lane after it).
+constexpr uint32_t kNoFlip = 63u << 24;
+
+// One-hot code of a lane's attempt: bit a (current state), bit 16 + b (proposed).
+__device__ __forceinline__ uint32_t state_code(int a, int b) { return (1u << a) | (1u << (b + 16)); }
+
+// Change of dE = h[a][i] - h[b][i] under a flip ap -> bp of another site, in
+// units of the coupling: [a=bp] - [a=ap] - [b=bp] + [b=ap], as two popcounts
+// of the lane's one-hot code (the flip's masks are wave-uniform).
+__device__ __forceinline__ int dE_coef(uint32_t code, uint32_t w)
+{
+    const uint32_t P = 1u << fw_old(w), Q = 1u << fw_new(w);  // ap == bp: both masks equal, c = 0
+    // the word is wave-uniform: pin the masks to scalar registers (one SGPR operand per AND)
+    const uint32_t X = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(Q | (P << 16))));
+    const uint32_t Y = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(P | (Q << 16))));
+    return static_cast<int>(__popc(code & X)) - static_cast<int>(__popc(code & Y));
 }
 
-// Wave 0: the chain through attempts [t0, t0 + 64) (lanes past `cend` idle).
-// Each lane keeps only the two fields its attempt needs, ha = h[a][i] and
-// hb = h[b][i].  The sequential chain is resolved by guess and check: every
-// attempt that is a sure accept under the current fields is guessed to be
-// accepted; the guessed flips are applied, in order, to the fields of the
-// later lanes (couplings gathered kFlipBatch flips at a time); the guess
+// dE of every lane after the flips lst[begin..end) (lane r of `lst` holds the
+// r-th flip word), in order, each applied only to the lanes after its own
+// (gate: lane > fw_lane): dE = fma(c, J*(|i-ip|), dE) with c in {-2..2}, one
+// rounding per flip.  The list is read at sequential indices, so the words of
+// a batch are fetched independently; couplings are gathered kFlipBatch flips
+// at a time and applied without branches (entries past `end` read as the
+// padding word), so a batch's gathers stay in flight together.
+template <typename F, bool D>
+__device__ __forceinline__ void apply_list(const Walker<F> &W, int L, int i, int lane, uint32_t code, uint32_t lst,
+                                           int begin, int end, double &dE)
+{
+    for (int p0 = begin; p0 < end; p0 += kFlipBatch) {
+        uint32_t wb[kFlipBatch];
+        F jb[kFlipBatch];
+#pragma unroll
+        for (int e = 0; e < kFlipBatch; ++e) {
+            const uint32_t r = static_cast<uint32_t>(rl_i(static_cast<int>(lst), (p0 + e) & (kWave - 1)));
+            wb[e] = p0 + e < end ? r : kNoFlip;
+            jb[e] = coupling_to<D>(W, L, i, fw_site(wb[e]));
+        }
+#pragma unroll
+        for (int e = 0; e < kFlipBatch; ++e) {
+            const int c = dE_coef(lane > fw_lane(wb[e]) ? code : 0u, wb[e]);  // code 0: no change
+            dE = fma(static_cast<double>(c), static_cast<double>(jb[e]), dE);
+        }
+    }
+}
+
+// The flips of the lanes in `set`, compacted in lane order: lane r of the
+// result holds the r-th one's word (ds_permute moves every lane's word to its
+// rank; lanes outside the set carry the padding word to the slots past them).
+__device__ __forceinline__ uint32_t compact_flips(uint64_t set, int lane, uint32_t word)
+{
+    const bool in = (set >> lane) & 1ull;
+    const int below = __popcll(set & lanes_below(lane));
+    const int slot = in ? below : __popcll(set) + (lane - below);
+    return static_cast<uint32_t>(__builtin_amdgcn_ds_permute(slot * 4, static_cast<int>(in ? word : kNoFlip)));
+}
+
+// Passes shorter than this run whole in every wave; longer ones are split.
+constexpr int kSplitMin = 8;
+
+// dE += the corrections of flips lst[begin..end), computed by the whole
+// workgroup.  Every wave holds the same 64 attempts; a short pass runs whole
+// in each wave (no exchange), a long one is split into contiguous shares, one
+// per wave, whose partial sums are exchanged through LDS (one barrier; the
+// buffer alternates between passes so a wave still reading one pass's
+// partials is never overwritten) and added in wave order, identically in
+// every wave.  Rounding of the split form: each partial is a difference of
+// two intermediate dE values (|.| <= 2 S), so the nw - 1 additions of
+// partials and the final addition add at most 2 units of 2 unit, counted in ex.
+template <typename F, bool D>
+__device__ __forceinline__ void add_flips_wg(const Walker<F> &W, int L, int i, int lane, uint32_t code, uint32_t lst,
+                                             int begin, int end, double &dE, int &ex, int &pbuf)
+{
+    const int nw = blockDim.x / kWave, wv = threadIdx.x / kWave;
+    const int n = end - begin;
+    if (nw == 1 || n < kSplitMin) {
+        apply_list<F, D>(W, L, i, lane, code, lst, begin, end, dE);
+        return;
+    }
+    const int per = (n + nw - 1) / nw;
+    const int b0 = min(end, begin + wv * per), b1 = min(end, b0 + per);
+    double part = 0.0;
+    apply_list<F, D>(W, L, i, lane, code, lst, b0, b1, part);
+    double *xp = W.xpart + pbuf * nw * kWave;
+    xp[wv * kWave + lane] = part;
+    __syncthreads();
+    double tot = xp[lane];
+    for (int k = 1; k < nw; ++k) tot += xp[k * kWave + lane];
+    pbuf ^= 1;
+    dE += tot;
+    ex += 2;
+}
+
+// dE = h[a][i] - h[b][i] as the chain sees it: the two table entries (window
+// start) plus the window's flips 0..np-1 (all earlier than any live lane).
+template <typename F, bool D>
+__device__ __forceinline__ double dE_now(const Walker<F> &W, int L, int a, int b, int i, int np, int &ex, int &pbuf)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    double dE = static_cast<double>(W.h[a * L + i]) - static_cast<double>(W.h[b * L + i]);
+    const uint32_t pv = lane < np ? W.pend[lane] : kNoFlip;
+    ex = 0;
+    // lane 64 in the gate: every listed flip counts
+    const int nw = blockDim.x / kWave;
+    if (nw == 1 || np < kSplitMin) {
+        apply_list<F, D>(W, L, i, kWave, state_code(a, b), pv, 0, np, dE);
+    } else {
+        const int wv = threadIdx.x / kWave, per = (np + nw - 1) / nw;
+        const int b0 = min(np, wv * per), b1 = min(np, b0 + per);
+        double part = 0.0;
+        apply_list<F, D>(W, L, i, kWave, state_code(a, b), pv, b0, b1, part);
+        double *xp = W.xpart + pbuf * nw * kWave;
+        xp[wv * kWave + lane] = part;
+        __syncthreads();
+        double tot = xp[lane];
+        for (int k = 1; k < nw; ++k) tot += xp[k * kWave + lane];
+        pbuf ^= 1;
+        dE += tot;
+        ex = 2;
+    }
+    return dE;
+}
+
+// The chain through attempts [t0, t0 + 64) (lanes past `cend` idle), run by
+// every wave of the workgroup on the same 64 attempts: all decisions are taken
+// identically in each wave, the long correction passes are split between the
+// waves (add_flips_wg), and the shared results (flip list, spins) are written
+// by every wave with the same values; counters, events and energy increments
+// are kept by wave 0 alone.  Each lane keeps its attempt's energy change
+// dE = h[a][i] - h[b][i] (a the current state of its site, b the proposed
+// one), read from the table once.
+// The sequential chain is resolved by guess and check: every attempt that is
+// a sure accept under the current dE is guessed to be accepted; the guess
 // stops at the first later attempt on a site a guessed flip changed, whose
-// state the guess cannot know.  Each lane then re-decides with exactly the
-// guessed flips before it, and its own bound.  Up to the first lane whose
+// state the guess cannot know; the guessed flips before it are applied, in
+// order, to the later lanes' dE.  Each lane then re-decides with exactly the
+// guessed flips before it and its own bound.  Up to the first lane whose
 // decision differs from the guess, every lane saw precisely the flips the
-// sequential chain would have accepted before it, so that prefix is committed;
-// the differing lane is decided (near-threshold ones by the FP64 direct sum),
-// and the later lanes' fields are rebuilt from the committed flips.  The
-// commit is the same arithmetic, in the same order, as taking the accepts one
-// by one.  Energy increments stay in the accepting lane (eL, errL) and are
+// sequential chain would have accepted before it, so that prefix is
+// committed; the differing lane is decided (near-threshold ones by the FP64
+// direct sum) and the later lanes' dE are rebuilt from the committed flips.
+// Committed flips write their spins at once; a later lane whose site changed
+// takes the new state and re-derives dE from the table and the window's
+// flips.  Energy increments stay in the accepting lane (eL, errL) and are
 // summed at the end of the sweep.
+//
+// Rounding: dE starts as the difference of two table entries (each within
+// init + nupd * unit of exact) and takes at most 2 unit of rounding per applied
+// flip, so Bd = 2 (init + nupd * unit) grown by 2 unit per flip bounds its
+// error exactly as for two separately kept fields; a split pass adds `ex`
+// more such units per lane.
 template <typename F, bool D>
 __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w, int64_t n, double beta, int t0,
-                                             int c0, int cend, ChainRegs &cr)
+                                             int c0, int cend, ChainRegs &cr, int &pbuf)
 {
     constexpr bool kF64 = sizeof(F) == sizeof(double);
-    constexpr int B = kFlipBatch;
     const int L = P.L, q = P.q, lane = threadIdx.x & (kWave - 1);
+    const bool lead = threadIdx.x < kWave;  // wave 0 keeps counters, events and energy increments
+    uint32_t *sfirst = W.sfirst ? W.sfirst + (threadIdx.x / kWave) * L : nullptr;
     const uint64_t mine_below = lanes_below(lane);
     const int ta = t0 + lane;
     const bool valid = ta < cend;
@@ -570,61 +683,57 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
     int a = W.sp[i];
     int b = a + kk;
     b -= b >= q ? q : 0;
-    F ha = W.h[a * L + i], hb = W.h[b * L + i];
-    uint64_t live = __ballot(valid);
+    double dE = static_cast<double>(W.h[a * L + i]) - static_cast<double>(W.h[b * L + i]);
+    uint32_t code = state_code(a, b);
+    int ex = 0;  // extra roundings in this lane's dE, in units of 2 unit
+    uint64_t live = ballot(valid);
     int np = 0;
     double Bd = 2.0 * (P.bound_init + static_cast<double>(cr.nupd) * P.bound_unit);
     const double dBd = 2.0 * P.bound_unit;
     const double tfix = kBand + kEvalMargin;
     while (live) {
-        const uint32_t pk = static_cast<uint32_t>(i) | (static_cast<uint32_t>(a) << 16) | (static_cast<uint32_t>(b) << 24);
-        // guess: the sure accepts under the current fields
-        double dE = static_cast<double>(ha) - static_cast<double>(hb);
-        uint64_t S = __ballot(beta * dE + lnu < -(beta * Bd + tfix)) & live;
-        const F ha0 = ha, hb0 = hb;
-        int hz = kWave;        // first lane on a site changed by a guessed flip before it
-        int sfl = -1, sb = 0;  // that flip's lane and new state, for this lane
-        uint64_t rem = S;
-        bool go = true;
-        while (rem && go) {
-            int pb[B];
-            uint32_t pkb[B];
-            F jb[B];
-#pragma unroll
-            for (int e = 0; e < B; ++e) {  // padding entries: lane 64, no flip
-                pb[e] = rem ? static_cast<int>(__builtin_ctzll(rem)) : kWave;
-                rem &= rem - 1ull;
-                pkb[e] = pb[e] < kWave ? static_cast<uint32_t>(rl_i(static_cast<int>(pk), pb[e])) : kNoFlip;
-                jb[e] = coupling_to<D>(W, L, i, static_cast<int>(pkb[e] & 0xFFFFu));
-            }
-            // applied without branches (a skipped entry corrects no lane), so
-            // the batch's gathers stay in flight together
-#pragma unroll
-            for (int e = 0; e < B; ++e) {
-                go = go && pb[e] < hz;
-                const bool after = go && lane > pb[e];
-                const bool same = valid && after && i == static_cast<int>(pkb[e] & 0xFFFFu);
-                const uint64_t st = __ballot(same);
-                hz = st ? min(hz, static_cast<int>(__builtin_ctzll(st))) : hz;
-                sfl = same ? pb[e] : sfl;
-                sb = same ? static_cast<int>(pkb[e] >> 24) : sb;
-                correct_fields(ha, hb, after, a, b, pkb[e], jb[e]);
+        const uint32_t pk = flip_word(i, a, b, lane);
+        // guess: the sure accepts under the current dE
+        uint64_t S = ballot(beta * dE + lnu < -(beta * Bd + tfix)) & live;
+        const bool inS0 = (S >> lane) & 1ull;
+        // the first lane after a guessed flip on its own site.  A guessed flip
+        // at or past that lane only meets lanes past it, so testing against
+        // all of S finds the same first lane as stopping there would.
+        uint64_t dm = 0;
+        if (S) {
+            if (sfirst) {  // this wave's per-site table: the first guessed lane on each site
+                if (inS0) atomicMin(&sfirst[i], static_cast<uint32_t>(lane));
+                const uint32_t f0 = sfirst[i];
+                dm = ballot(valid && f0 < static_cast<uint32_t>(lane));
+                if (inS0) sfirst[i] = kWave;
+            } else {
+                for (uint64_t sm = S; sm; sm &= sm - 1ull) {
+                    const int p = static_cast<int>(__builtin_ctzll(sm));
+                    dm |= ballot(valid && lane > p && i == rl_i(i, p));
+                }
             }
         }
+        const int hz = dm ? static_cast<int>(__builtin_ctzll(dm)) : kWave;
         S &= lanes_below(hz);
+        const double dE0 = dE;
+        const int ex0 = ex;
+        const uint32_t lst = compact_flips(S, lane, pk);  // lane r: the r-th guessed flip
+        add_flips_wg<F, D>(W, L, i, lane, code, lst, 0, __popcll(S), dE, ex, pbuf);
         // check: each lane decides with the guessed flips before it
-        dE = static_cast<double>(ha) - static_cast<double>(hb);
         const double x = beta * dE + lnu;
         const int r = __popcll(S & mine_below);
-        const double Bdl = Bd + static_cast<double>(r) * dBd;
+        const double Bdl = Bd + static_cast<double>(r + ex) * dBd;
         const double trig = beta * Bdl + tfix;
         const bool inS = (S >> lane) & 1ull;
         const bool sure = x < -trig, rej = x > trig;
-        const uint64_t V = __ballot(inS ? !sure : !rej) & live & lanes_below(hz);
+        const uint64_t V = ballot(inS ? !sure : !rej) & live & lanes_below(hz);
         const int m = V ? static_cast<int>(__builtin_ctzll(V)) : hz;
         const uint64_t C = S & lanes_below(m);
-        if ((C >> lane) & 1ull) {
+        if ((C >> lane) & 1ull) {  // committed lanes have distinct sites
             W.pend[np + r] = pk;
+            W.sp[i] = static_cast<uint8_t>(b);
+        }
+        if (lead && ((C >> lane) & 1ull)) {
             atomicAdd(&W.cnt[a], -1);
             atomicAdd(&W.cnt[b], 1);
             if (kF64) {  // FP32 tables take E from the flush's exact sums
@@ -637,22 +746,20 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
         cr.nupd += nc;
         cr.nacc += nc;
         Bd += static_cast<double>(nc) * dBd;
-        bool stale = sfl >= 0 && sfl < m;  // a committed flip changed this lane's site
         if (V) {
             // lane m holds exactly the committed flips: decide it
             const uint32_t pk_m = static_cast<uint32_t>(rl_i(static_cast<int>(pk), m));
-            const int i_m = static_cast<int>(pk_m & 0xFFFFu), a_m = static_cast<int>((pk_m >> 16) & 0xFFu),
-                      b_m = static_cast<int>(pk_m >> 24);
-            bool accept = (__ballot(sure) >> m) & 1ull;
-            double dEm = rl_d(dE, m), errm = Bd;
-            if (!accept && !((__ballot(rej) >> m) & 1ull)) {
+            const int i_m = fw_site(pk_m), a_m = fw_old(pk_m), b_m = fw_new(pk_m);
+            bool accept = (ballot(sure) >> m) & 1ull;
+            double dEm = rl_d(dE, m), errm = Bd + static_cast<double>(rl_i(ex, m)) * dBd;
+            if (!accept && !((ballot(rej) >> m) & 1ull)) {
                 // |x| inside the trigger band: decide with the FP64 direct sum
-                const double d64 = chain_direct_dE(W, L, i_m, a_m, b_m, np);
+                const double d64 = chain_direct_dE(W, L, i_m, a_m, b_m);
                 const double x64 = beta * d64 + rl_d(lnu, m);
                 accept = x64 < 0.0;
                 dEm = d64;
                 errm = 0.0;
-                if (lane == 0) {
+                if (lead && lane == 0) {
                     atomicAdd(&P.ctr[kCtrRecheck], 1ull);
                     if (fabs(x64) <= kBand) {
                         atomicAdd(&P.ctr[kCtrBandedMet], 1ull);
@@ -660,27 +767,16 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
                     }
                 }
             }
-            // rebuild the later lanes' fields from the committed flips
-            ha = ha0;
-            hb = hb0;
-            uint64_t cm = C;
-            while (cm) {
-                int pb[B];
-                uint32_t pkb[B];
-                F jb[B];
-#pragma unroll
-                for (int e = 0; e < B; ++e) {
-                    pb[e] = cm ? static_cast<int>(__builtin_ctzll(cm)) : kWave;
-                    cm &= cm - 1ull;
-                    pkb[e] = pb[e] < kWave ? static_cast<uint32_t>(rl_i(static_cast<int>(pk), pb[e])) : kNoFlip;
-                    jb[e] = coupling_to<D>(W, L, i, static_cast<int>(pkb[e] & 0xFFFFu));
-                }
-#pragma unroll
-                for (int e = 0; e < B; ++e) correct_fields(ha, hb, lane > pb[e], a, b, pkb[e], jb[e]);
-            }
+            // rebuild the later lanes' dE from the committed flips (the list's first nc)
+            dE = dE0;
+            ex = ex0;
+            add_flips_wg<F, D>(W, L, i, lane, code, lst, 0, nc, dE, ex, pbuf);
             if (accept) {
                 if (lane == m) {
                     W.pend[np] = pk_m;
+                    W.sp[i_m] = static_cast<uint8_t>(b_m);
+                }
+                if (lead && lane == m) {
                     atomicAdd(&W.cnt[a_m], -1);
                     atomicAdd(&W.cnt[b_m], 1);
                     if (kF64) {
@@ -692,26 +788,34 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
                 ++cr.nupd;
                 ++cr.nacc;
                 Bd += dBd;
-                correct_fields(ha, hb, lane > m, a, b, pk_m, coupling_to<D>(W, L, i, i_m));
-                if (lane > m && i == i_m) {
-                    stale = true;
-                    sb = b_m;
-                }
+                const int c = dE_coef(lane > m ? code : 0u, pk_m);
+                dE = fma(static_cast<double>(c), static_cast<double>(coupling_to<D>(W, L, i, i_m)), dE);
             }
             live &= ~lanes_below(m + 1);
         } else {
             live &= ~lanes_below(hz);
         }
-        // later lanes on a flipped site: new current state, fields re-derived
-        if (stale && ((live >> lane) & 1ull)) {
-            a = sb;
-            b = a + kk;
-            b -= b >= q ? q : 0;
-            ha = field_now(W, L, a, i, np);
-            hb = field_now(W, L, b, i, np);
+        // a later lane whose site's spin changed: new current state, dE re-derived
+        const int sn = W.sp[i];
+        const bool redo = ((live >> lane) & 1ull) && sn != a;
+        if (ballot(redo)) {
+            int b2 = sn + kk;
+            b2 -= b2 >= q ? q : 0;
+            int ex2;
+            const double dE2 = dE_now<F, D>(W, L, redo ? sn : a, redo ? b2 : b, i, np, ex2, pbuf);
+            if (redo) {
+                a = sn;
+                b = b2;
+                code = state_code(a, b);
+                dE = dE2;
+                ex = ex2;
+            }
         }
+        // every wave has finished reading this iteration's spins before any
+        // wave writes the next iteration's commits
+        if (blockDim.x > kWave) __syncthreads();
     }
-    if (lane == 0) W.cs->np[(t0 / kWave) & 1] = np;
+    if (lead && lane == 0) W.cs->np[(t0 / kWave) & 1] = np;
 }
 
 // Whole workgroup: apply the window's np flips to the table.  Each thread
@@ -725,19 +829,16 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
 // are applied; with a doubled coupling row (D) one address serves a flip's
 // kFlushM gathers.  With an FP32 table the same pass forms the exact FP64
 // energy change of every flip, sum_j J*(|j-i|)[delta(a, s_j) - delta(b, s_j)],
-// over the spins as they were just before it (partial sums per thread).
+// over the spins as they were just before it (partial sums per thread; the
+// window-start spins are recovered from the flip list, since the chain has
+// already written the new ones).
 template <typename F, int QT, bool D>
 __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np, double &part)
 {
     constexpr int M = kFlushM, B = kFlipBatch;
     constexpr bool kF32 = sizeof(F) == sizeof(float);
     const int L = P.L, q = P.q, tid = threadIdx.x, NT = blockDim.x, lane = tid & (kWave - 1);
-    const uint32_t pv = lane < np ? W.pend[lane] : kNoFlip;
-    if (!kF32 && tid == 0)
-        for (int p = 0; p < np; ++p) {
-            const uint32_t pk = static_cast<uint32_t>(rl_i(static_cast<int>(pv), p));
-            W.sp[pk & 0xFFFFu] = static_cast<uint8_t>(pk >> 24);
-        }
+    const uint32_t pv = lane < np ? W.pend[lane] : kNoFlip;  // the chain already wrote the spins
     for (int jb = (tid / kWave) * kWave * M; jb < L; jb += NT * M) {
         const int j0 = jb + lane;
         int jm[M];
@@ -750,6 +851,14 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
             ok[m] = j < L;
             jm[m] = ok[m] ? j : 0;
             sr[m] = (kF32 && ok[m]) ? W.sp[j] : -1;
+        }
+        if (kF32) {  // back to the window's start: the first flip of a site holds its old state
+            for (int p = np - 1; p >= 0; --p) {
+                const uint32_t pk = static_cast<uint32_t>(rl_i(static_cast<int>(pv), p));
+                const int ip = fw_site(pk), ap = fw_old(pk);
+#pragma unroll
+                for (int m = 0; m < M; ++m) sr[m] = (ok[m] && jm[m] == ip) ? ap : sr[m];
+            }
         }
 #pragma unroll
         for (int c = 0; c < QT; ++c)
@@ -765,7 +874,7 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
             for (int e = 0; e < B; ++e) {
                 // p0 + e <= 63; lanes past np hold the no-flip word
                 pkb[e] = static_cast<uint32_t>(rl_i(static_cast<int>(pv), p0 + e));
-                const int ip = static_cast<int>(pkb[e] & 0xFFFFu);
+                const int ip = fw_site(pkb[e]);
 #pragma unroll
                 for (int m = 0; m < M; ++m) {
                     int d = jm[m] - ip;
@@ -780,8 +889,7 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
 #pragma unroll
             for (int e = 0; e < B; ++e) {
                 const bool real = p0 + e < np;
-                const int ip = static_cast<int>(pkb[e] & 0xFFFFu), ap = static_cast<int>((pkb[e] >> 16) & 0xFFu),
-                          bp = static_cast<int>(pkb[e] >> 24);
+                const int ip = fw_site(pkb[e]), ap = fw_old(pkb[e]), bp = fw_new(pkb[e]);
                 if constexpr (QT > 0) {  // no branch: padding entries have all coefficients 0
 #pragma unroll
                     for (int c = 0; c < QT; ++c) {
@@ -802,7 +910,7 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
 #pragma unroll
                     for (int m = 0; m < M; ++m) {
                         const int s = sr[m];
-                        part += s == ap ? g64[e][m] : (s == bp ? -g64[e][m] : 0.0);
+                        part += (real && s == ap) ? g64[e][m] : ((real && s == bp) ? -g64[e][m] : 0.0);
                         sr[m] = (real && ok[m] && jm[m] == ip) ? bp : s;
                     }
                 }
@@ -813,11 +921,6 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
 #pragma unroll
             for (int m = 0; m < M; ++m)
                 if (c < q && ok[m]) W.h[c * L + jm[m]] = hr[c][m];
-        if (kF32) {
-#pragma unroll
-            for (int m = 0; m < M; ++m)
-                if (ok[m]) W.sp[jm[m]] = static_cast<uint8_t>(sr[m]);
-        }
     }
 }
 
@@ -826,14 +929,15 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
 template <typename F, int QT, bool D>
 __device__ __forceinline__ double sweep_walker(const Inst &P, Walker<F> &W, int w, int64_t n, double beta, ChainRegs &cr)
 {
-    const int L = P.L, wave = threadIdx.x / kWave;
+    const int L = P.L;
     double part = 0.0;
+    int pbuf = 0;
     for (int c0 = 0; c0 < L; c0 += W.chunk) {
         const int cend = min(L, c0 + W.chunk);
         gen_draws<F>(P, W, w, n, c0, cend - c0);
         __syncthreads();
         for (int t0 = c0; t0 < cend; t0 += kWave) {
-            if (wave == 0) chain_window<F, D>(P, W, w, n, beta, t0, c0, cend, cr);
+            chain_window<F, D>(P, W, w, n, beta, t0, c0, cend, cr, pbuf);
             __syncthreads();
             const int np = W.cs->np[(t0 / kWave) & 1];
             if (np > 0) {
