@@ -116,6 +116,7 @@ bool make_plan_chunk(int L, int q, int R, int prec, bool fused, bool h_in_lds, s
     }
     const int nw = threads / kWave;
     p->xpart = o; o = align16(o + 2 * nw * kWave * 8);
+    p->ctab = o; o = align16(o + 256 * fb);
     // optional: the chain's first-guessed-flip tables (4 B per site and wave)
     if (static_cast<size_t>(o) + 4u * L * nw <= lds_max) {
         p->sfirst = o;

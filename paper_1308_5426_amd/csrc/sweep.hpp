@@ -35,6 +35,7 @@ struct LdsPlan {
     int32_t jlen;         // entries of the coupling row J: L, or L + flush span when doubled
     int32_t sfirst;       // [waves][L] u32 first-guessed-flip tables, or -1 when they do not fit
     int32_t xpart;        // [2][waves][64] FP64 partial corrections exchanged between waves
+    int32_t ctab;         // [64][4] flush coefficients (table precision) by flip kind
 };
 
 // Flush geometry: in each pass every wave owns kFlushM blocks of 64
@@ -76,6 +77,7 @@ struct Walker {
     uint32_t *pend;     // [64] flip words of the flips accepted in the current window
     uint32_t *sfirst;   // [waves][L] per site: first lane of the current guess flipping it (64: none), or null
     double *xpart;      // [2][waves][64] partial corrections of the split passes
+    F *ctab;            // [64][4] row coefficients of a flip of kind old + 16 new (states < 4)
     ChainState *cs;
     int32_t chunk;
 };
@@ -107,6 +109,7 @@ __device__ __forceinline__ Walker<F> carve(unsigned char *lds, const LdsPlan &p,
     W.cs = reinterpret_cast<ChainState *>(lds + p.cs);
     W.sfirst = p.sfirst >= 0 ? reinterpret_cast<uint32_t *>(lds + p.sfirst) : nullptr;
     W.xpart = reinterpret_cast<double *>(lds + p.xpart);
+    W.ctab = reinterpret_cast<F *>(lds + p.ctab);
     W.chunk = p.chunk;
     return W;
 }
@@ -152,6 +155,16 @@ __global__ void k_init_spins(Inst P, int32_t ordered)
 // ---------------------------------------------------------------------------
 // Walker state HBM <-> LDS.
 // ---------------------------------------------------------------------------
+// Change of the field of state c under a flip ap -> bp, in units of the
+// coupling: -1 if c was the old state, +1 if c is the new one, else 0.  Applied
+// as fma(coef, J, h), which rounds exactly as h - J or h + J (or leaves h).
+template <typename F>
+__device__ __forceinline__ F flip_coef(int c, int ap, int bp)
+{
+    // +1 for the new state, -1 for the old one; 0 otherwise, and for ap == bp (no flip)
+    return c == bp ? (c == ap ? F(0) : F(1)) : (c == ap ? F(-1) : F(0));
+}
+
 template <typename F>
 __device__ __forceinline__ void load_walker(const Inst &P, Walker<F> &W, const LdsPlan &plan, int w)
 {
@@ -166,6 +179,11 @@ __device__ __forceinline__ void load_walker(const Inst &P, Walker<F> &W, const L
     }
     if (W.sfirst)
         for (int k = threadIdx.x; k < (blockDim.x / kWave) * L; k += blockDim.x) W.sfirst[k] = kWave;
+    // coefficient of row c under a flip ap -> bp, kind ap + 16 bp (kind 0: no flip)
+    for (int e = threadIdx.x; e < 256; e += blockDim.x) {
+        const int k = e >> 2, c = e & 3;
+        W.ctab[e] = flip_coef<F>(c, k & 15, k >> 4);
+    }
     // J[k] = J*(k mod L): with a doubled row, J*(|j - i|) = J[j - i + L] needs no wrap
     for (int k = threadIdx.x; k < plan.jlen; k += blockDim.x) W.J[k] = Jsrc[k % L];
     if (plan.h_in_lds)
@@ -476,8 +494,6 @@ __device__ __forceinline__ uint64_t lanes_below(int l) { return l >= kWave ? ~0u
 
 template <bool D, typename F>
 __device__ __forceinline__ F coupling_to(const Walker<F> &W, int L, int i, int ip);
-template <typename F>
-__device__ __forceinline__ F flip_coef(int c, int ap, int bp);
 
 // Coupling J*(|i - ip|) of site i to site ip.  D: the row is doubled
 // (J[k] = J*(k mod L) for k < L + span), so no wrap is needed.
@@ -491,16 +507,6 @@ __device__ __forceinline__ F coupling_to(const Walker<F> &W, int L, int i, int i
         d += d < 0 ? L : 0;
         return W.J[d];  // J*(0) = 0 on the flipped site itself
     }
-}
-
-// Change of the field of state c under a flip ap -> bp, in units of the
-// coupling: -1 if c was the old state, +1 if c is the new one, else 0.  Applied
-// as fma(coef, J, h), which rounds exactly as h - J or h + J (or leaves h).
-template <typename F>
-__device__ __forceinline__ F flip_coef(int c, int ap, int bp)
-{
-    // +1 for the new state, -1 for the old one; 0 otherwise, and for ap == bp (no flip)
-    return c == bp ? (c == ap ? F(0) : F(1)) : (c == ap ? F(-1) : F(0));
 }
 
 // Flip word: site (bits 0-15), old state (16-19), new state (20-23), and the
@@ -891,9 +897,10 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
                 const bool real = p0 + e < np;
                 const int ip = fw_site(pkb[e]), ap = fw_old(pkb[e]), bp = fw_new(pkb[e]);
                 if constexpr (QT > 0) {  // no branch: padding entries have all coefficients 0
+                    const F *kc = W.ctab + ((pkb[e] >> 16) & 0x3Fu) * 4;  // one broadcast row per flip
 #pragma unroll
                     for (int c = 0; c < QT; ++c) {
-                        const F k = flip_coef<F>(c, ap, bp);
+                        const F k = kc[c];
 #pragma unroll
                         for (int m = 0; m < M; ++m) hr[c][m] = fma(k, g[e][m], hr[c][m]);
                     }
