@@ -231,14 +231,20 @@ def lds_peak_measured():
 
 
 def load_traffic(sha, name):
+    """HBM bytes per launch of the sweep kernel from a committed counter
+    summary (lines `key: value`), if it was taken on these kernel sources."""
     p = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(p):
         return None
+    d = {}
     with open(p) as f:
-        d = json.load(f)
-    if d.get("source_sha") != sha:
+        for line in f:
+            if ":" in line and not line.startswith(("#", "`", " ", "|")):
+                k, v = line.split(":", 1)
+                d[k.strip()] = v.strip()
+    if d.get("source_sha") != sha or "hbm_bytes_per_launch" not in d:
         return None
-    return d
+    return {"hbm_bytes_per_launch": float(d["hbm_bytes_per_launch"])}
 
 
 def main():
@@ -255,7 +261,10 @@ def main():
     ap.add_argument("--arena-gb", type=float, default=16.0, help="serve: device arena")
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--lds", type=int, default=0)
-    ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--precision", default="f64", choices=["f32", "f64"])
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="first copy this many bytes device to device (a kernel of known HBM traffic, "
+                         "to calibrate the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--sweeps", type=int, default=0, help="override the workload's sweep count")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -273,6 +282,15 @@ def main():
         print(json.dumps(out), flush=True)
         return
 
+    if args.copy_bytes:
+        import torch
+
+        src = torch.ones(args.copy_bytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     inst = workload(args.workload)
     if args.sweeps:
         inst.sweeps = args.sweeps
@@ -284,7 +302,7 @@ def main():
     bytes_, acc = algorithmic_bytes(obs, inst.L, attempts, inst.R * inst.sweeps, prec)
     achieved = bytes_ / kern
     sha = kernel_source_sha()
-    tr = load_traffic(sha, f"pmc_k_sweep_{args.workload}_{args.precision}.json")
+    tr = load_traffic(sha, f"pmc_k_sweep_{args.workload}_{args.precision}.md")
     traffic = None if tr is None else tr["hbm_bytes_per_launch"]
     occupied = min(CUS, inst.R)
     lds_meas = lds_peak_measured()
