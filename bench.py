@@ -74,10 +74,19 @@ def run_gpu(inst, prec, steps, warmup, max_chunk=0):
                              max_sweeps_per_launch=max_chunk or inst.sweeps)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
+        print(f"[bench] instance ready, running {inst.sweeps} sweeps", file=sys.stderr, flush=True)
         e0.record(stream)
-        sim.run(inst.sweeps, 1)
+        done = 0
+        while done < inst.sweeps:  # long runs go in launches of max_chunk sweeps, each reported
+            n = min(inst.sweeps - done, max_chunk or inst.sweeps)
+            sim.run(n, 1)
+            done += n
+            if done < inst.sweeps:
+                sim.synchronize()
+                print(f"[bench] {done} sweeps", file=sys.stderr, flush=True)
         e1.record(stream)
         obs = sim.observables()  # synchronises
+        print(f"[bench] sweeps done in {e0.elapsed_time(e1) / 1e3:.2f} s", file=sys.stderr, flush=True)
         if timed:
             t_kernel.append(e0.elapsed_time(e1) / 1e3)
             obs_last = obs
@@ -143,16 +152,19 @@ def run_batch(args):
         b.close()
         if it >= args.warmup:
             times.append(dt)
+        print(f"[batch] step {it} ({'timed' if it >= args.warmup else 'warm-up'}) {dt:.2f} s", file=sys.stderr,
+              flush=True)
     el = sum(times)
     # plain per-instance GPU form: the same jobs one pt_init/pt_run at a time
     k = min(args.plain_sample, len(jd))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for j in jd[:k]:
+    for n_done, j in enumerate(jd[:k]):
         sim = pkg.Simulation(j["L"], j["q"], j["sigma"], j["T"], j["seed"], precision=prec)
         sim.run(j["sweeps"], 1)
         sim.observables()
         sim.close()
+        print(f"[batch] plain job {n_done} done", file=sys.stderr, flush=True)
     dt_plain = time.perf_counter() - t0
     att_plain = sum(j["L"] * len(j["T"]) * j["sweeps"] for j in jd[:k])
     return {
@@ -295,7 +307,8 @@ def main():
     if args.sweeps:
         inst.sweeps = args.sweeps
     prec = 1 if args.precision == "f32" else 0
-    elapsed, tk, obs = run_gpu(inst, prec, args.steps, args.warmup)
+    # the L = 16384 instance runs in launches of 250 sweeps (progress between them)
+    elapsed, tk, obs = run_gpu(inst, prec, args.steps, args.warmup, max_chunk=250 if inst.L > 8192 else 0)
     attempts = inst.L * inst.R * inst.sweeps
     value = attempts * args.steps / elapsed
     kern = sum(tk) / len(tk)

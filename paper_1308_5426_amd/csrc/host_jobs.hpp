@@ -199,6 +199,23 @@ pt_status pt_batch_create(pt_batch **out, const pt_job_desc *jobs, int32_t njobs
     b->prec = o.precision;
     b->stream = static_cast<hipStream_t>(o.stream);
     if ((st = shape_defaults(o, b->prec, &b->threads, &b->budget)) != PT_OK) return bail(st);
+    if (o.lds_budget <= 0) {
+        // default budget: raised, in 4 KiB steps up to what the device allows,
+        // until the largest job fits with its table in HBM
+        int cap = 0, dev = 0;
+        hipFuncAttributes fa;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cap, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+            hipFuncGetAttributes(&fa, jobs_fn_prec(b->prec)) != hipSuccess)
+            return bail(fail(PT_EDEVICE, "device query failed"));
+        cap = (cap - static_cast<int>(fa.sharedSizeBytes)) & ~255;
+        for (int j = 0; j < njobs; ++j) {
+            LdsPlan pl;
+            while (b->budget < cap &&
+                   !make_plan(jobs[j].L, jobs[j].q, jobs[j].R, b->prec, true, false, b->budget, b->threads, &pl))
+                b->budget = std::min(cap, b->budget + 4096);
+        }
+    }
     if (o.workspace) {
         if (o.workspace_bytes < b->total) return bail(fail(PT_ENOMEM, "workspace of %zu B < %zu B", o.workspace_bytes, b->total));
         b->ws = static_cast<unsigned char *>(o.workspace);

@@ -82,6 +82,7 @@ bool make_plan_chunk(int L, int q, int R, int prec, bool fused, bool h_in_lds, s
 {
     const int32_t fb = static_cast<int32_t>(field_bytes(prec));
     const int nblk = (L + kWave - 1) / kWave;
+    const int nw = threads / kWave;
     // with the table in LDS the coupling row is doubled and padded to the
     // flush's site slots: J[k] = J*(k mod L) for k < L + passes * threads * kFlushM
     const int span = threads * kFlushM;
@@ -91,18 +92,25 @@ bool make_plan_chunk(int L, int q, int R, int prec, bool fused, bool h_in_lds, s
     p->h_in_lds = h_in_lds ? 1 : 0;
     p->h = o;
     if (h_in_lds) o = align16(o + fb * q * L);
-    p->masks = o; o = align16(o + 8 * q * nblk);
     p->sp = o; o = align16(o + L);
     p->cnt = o; o = align16(o + 4 * kQMax);
     p->red = o; o = align16(o + 8 * 32);
     p->misc = o; o = align16(o + 4 * 8);
-    p->chunk = chunk;
-    p->draw = o; o = align16(o + 4 * p->chunk);
-    p->dlnu = o; o = align16(o + 8 * p->chunk);
     p->pend = o; o = align16(o + 4 * kWave);
     p->cs = o; o = align16(o + static_cast<int32_t>(sizeof(ChainState)));
+    p->ctab = o; o = align16(o + 256 * fb);
+    // one scratch region for three uses that never overlap in time: the
+    // refresh's per-state site masks, the exchange step's scratch, and the
+    // sweep's staging (draws, ln u, the waves' partial corrections)
+    p->chunk = chunk;
+    const int32_t sweep_bytes = align16(4 * chunk) + align16(8 * chunk) + align16(2 * nw * kWave * 8);
+    const int32_t scratch = std::max({align16(8 * q * nblk), fused ? align16(40 * R) : 0, sweep_bytes});
+    p->masks = o;
     p->xch = o;
-    if (fused) o = align16(o + 40 * R);
+    p->draw = o;
+    p->dlnu = p->draw + align16(4 * chunk);
+    p->xpart = p->dlnu + align16(8 * chunk);
+    o += scratch;
     if (prec == PT_PREC_F64) {
         p->J64 = p->J;
         p->j64_in_lds = 1;
@@ -114,9 +122,6 @@ bool make_plan_chunk(int L, int q, int R, int prec, bool fused, bool h_in_lds, s
         p->J64 = 0;
         p->j64_in_lds = 0;
     }
-    const int nw = threads / kWave;
-    p->xpart = o; o = align16(o + 2 * nw * kWave * 8);
-    p->ctab = o; o = align16(o + 256 * fb);
     // optional: the chain's first-guessed-flip tables (4 B per site and wave)
     if (static_cast<size_t>(o) + 4u * L * nw <= lds_max) {
         p->sfirst = o;
@@ -128,10 +133,11 @@ bool make_plan_chunk(int L, int q, int R, int prec, bool fused, bool h_in_lds, s
     return static_cast<size_t>(o) <= lds_max;
 }
 
-// LDS carve: couplings, field table, FP64 couplings (if they fit), per-state
-// site masks, spins, counts, reduction scratch, flags, staged draws (the
-// largest chunk of 64..1024 attempts that fits), pending flips, exchange
-// scratch.
+// LDS carve: couplings, field table, spins, counts, reduction scratch, flags,
+// pending flips, flush coefficients, one shared scratch region (refresh
+// masks / exchange scratch / staged draws of the largest chunk of 64..1024
+// attempts that fits), FP64 couplings and the first-guessed-flip tables when
+// they fit.
 bool make_plan(int L, int q, int R, int prec, bool fused, bool h_in_lds, size_t lds_max, int threads, LdsPlan *p)
 {
     const int lmax = std::min(1024, ((L + kWave - 1) / kWave) * kWave);

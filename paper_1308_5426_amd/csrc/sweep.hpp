@@ -825,15 +825,17 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
 }
 
 // Whole workgroup: apply the window's np flips to the table.  Each thread
-// owns kFlushM sites per pass and applies the flips to them in order, so no
+// owns M sites per pass and applies the flips to them in order, so no
 // barrier is needed between flips.  QT > 0: the sites' q <= QT fields sit in
 // registers for the pass (one table read and write per field) and every flip
 // is applied to all of them as fma(coef, J, h) with a wave-uniform
-// coefficient (-1, 0 or +1), which rounds exactly as h - J or h + J; QT = 0:
-// the two rows a flip touches are updated in LDS directly (fewer registers,
-// for larger q).  The couplings of kFlipBatch flips are gathered before they
-// are applied; with a doubled coupling row (D) one address serves a flip's
-// kFlushM gathers.  With an FP32 table the same pass forms the exact FP64
+// coefficient (-1, 0 or +1, from a table by flip kind), which rounds exactly
+// as h - J or h + J; QT = 0 (larger q): per batch of flips, the rows the
+// batch touches are updated one after another, each entry read and written
+// once per batch, the next row's read in flight during this row's update.
+// The couplings of
+// kFlipBatch flips are gathered before they are applied; with a doubled
+// coupling row (D) one address serves a flip's kFlushM gathers.  With an FP32 table the same pass forms the exact FP64
 // energy change of every flip, sum_j J*(|j-i|)[delta(a, s_j) - delta(b, s_j)],
 // over the spins as they were just before it (partial sums per thread; the
 // window-start spins are recovered from the flip list, since the chain has
@@ -841,7 +843,9 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
 template <typename F, int QT, bool D>
 __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np, double &part)
 {
-    constexpr int M = kFlushM, B = kFlipBatch;
+    constexpr int QR = QT > 0 ? QT : 1;  // rows held in registers (q <= 4)
+    constexpr int M = kFlushM;
+    constexpr int B = kFlipBatch;
     constexpr bool kF32 = sizeof(F) == sizeof(float);
     const int L = P.L, q = P.q, tid = threadIdx.x, NT = blockDim.x, lane = tid & (kWave - 1);
     const uint32_t pv = lane < np ? W.pend[lane] : kNoFlip;  // the chain already wrote the spins
@@ -849,7 +853,7 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
         const int j0 = jb + lane;
         int jm[M];
         bool ok[M];
-        F hr[QT > 0 ? QT : 1][M];
+        F hr[QR][M];
         int sr[M];
 #pragma unroll
         for (int m = 0; m < M; ++m) {
@@ -896,7 +900,8 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
             for (int e = 0; e < B; ++e) {
                 const bool real = p0 + e < np;
                 const int ip = fw_site(pkb[e]), ap = fw_old(pkb[e]), bp = fw_new(pkb[e]);
-                if constexpr (QT > 0) {  // no branch: padding entries have all coefficients 0
+                // no branch per flip: padding entries have all coefficients 0
+                if constexpr (QT > 0) {
                     const F *kc = W.ctab + ((pkb[e] >> 16) & 0x3Fu) * 4;  // one broadcast row per flip
 #pragma unroll
                     for (int c = 0; c < QT; ++c) {
@@ -904,14 +909,6 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
 #pragma unroll
                         for (int m = 0; m < M; ++m) hr[c][m] = fma(k, g[e][m], hr[c][m]);
                     }
-                } else if (real) {
-                    F *ra = W.h + ap * L, *rb = W.h + bp * L;
-#pragma unroll
-                    for (int m = 0; m < M; ++m)
-                        if (ok[m]) {
-                            ra[jm[m]] -= g[e][m];
-                            rb[jm[m]] += g[e][m];
-                        }
                 }
                 if (kF32) {
 #pragma unroll
@@ -920,6 +917,40 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
                         part += (real && s == ap) ? g64[e][m] : ((real && s == bp) ? -g64[e][m] : 0.0);
                         sr[m] = (real && ok[m] && jm[m] == ip) ? bp : s;
                     }
+                }
+            }
+            if constexpr (QT == 0) {
+                // larger q: the rows this batch touches, one after another; each
+                // entry is read once, takes the batch's flips in order and is
+                // written once, and the next row's read is issued before this
+                // row's write (no write-to-read wait; the table may be in HBM)
+                uint32_t rows = 0;
+#pragma unroll
+                for (int e = 0; e < B; ++e) rows |= (1u << fw_old(pkb[e])) | (1u << fw_new(pkb[e]));
+                int c = static_cast<int>(__builtin_ctz(rows));  // rows != 0: padding touches row 0
+                F vn[M];
+#pragma unroll
+                for (int m = 0; m < M; ++m) vn[m] = ok[m] ? W.h[c * L + jm[m]] : F(0);
+                while (c >= 0) {
+                    F v[M];
+#pragma unroll
+                    for (int m = 0; m < M; ++m) v[m] = vn[m];
+                    rows &= rows - 1u;
+                    const int cn = rows ? static_cast<int>(__builtin_ctz(rows)) : -1;
+                    if (cn >= 0) {
+#pragma unroll
+                        for (int m = 0; m < M; ++m) vn[m] = ok[m] ? W.h[cn * L + jm[m]] : F(0);
+                    }
+#pragma unroll
+                    for (int e = 0; e < B; ++e) {
+                        const F k = flip_coef<F>(c, fw_old(pkb[e]), fw_new(pkb[e]));  // padding: 0
+#pragma unroll
+                        for (int m = 0; m < M; ++m) v[m] = fma(k, g[e][m], v[m]);
+                    }
+#pragma unroll
+                    for (int m = 0; m < M; ++m)
+                        if (ok[m]) W.h[c * L + jm[m]] = v[m];
+                    c = cn;
                 }
             }
         }
