@@ -191,9 +191,12 @@ def run_serve(args):
 
     stream = workloads.serve_stream(rate=args.rate, duration=args.duration)
     prec = 1 if args.precision == "f32" else 0
+    # synchronise before the server starts: a device-wide synchronisation would
+    # wait for the server's resident kernel, which runs until stop()
+    torch.cuda.synchronize()
     srv = pkg.Server(arena_bytes=int(args.arena_gb * (1 << 30)), max_jobs=len(stream) + 16, precision=prec,
                      threads=args.threads, lds_budget=args.lds)
-    torch.cuda.synchronize()
+    print(f"[serve] server up, {len(stream)} jobs to submit", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     ids = []
     for (ta, inst) in stream:
@@ -205,8 +208,10 @@ def run_serve(args):
         if len(ids) % 200 == 0:
             print(f"[serve] submitted {len(ids)} at t={time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     lat, done_t, att = [], [], 0
-    for (ta, inst, jid) in ids:
+    for n_done, (ta, inst, jid) in enumerate(ids):
         srv.wait(jid, timeout=600)
+        if n_done % 100 == 99:
+            print(f"[serve] {n_done + 1} results", file=sys.stderr, flush=True)
         sub, adm, fin = srv.times(jid)
         lat.append(fin - sub)
         done_t.append(fin)

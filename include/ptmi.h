@@ -218,7 +218,10 @@ pt_status pt_batch_free(pt_batch *b);
 typedef struct pt_server pt_server;
 
 /* arena_bytes of device memory for job state (opt->workspace may supply it);
- * max_jobs bounds the number of submissions over the server's life. */
+ * max_jobs bounds the number of submissions over the server's life.  The
+ * server's kernel stays resident until pt_server_stop: a device-wide
+ * synchronisation (hipDeviceSynchronize) issued by the caller while the server
+ * runs never returns. */
 pt_status pt_server_start(pt_server **out, size_t arena_bytes, int32_t max_jobs, const pt_options *opt);
 /* Queues a job (T copied); *id_out receives its id.  Thread-safe. */
 pt_status pt_server_submit(pt_server *s, const pt_job_desc *job, int64_t *id_out);

@@ -407,7 +407,9 @@ class Batch:
 
 class Server:
     """Continuous batching: a persistent launch that takes jobs while it runs
-    (pt_server).  Jobs wait until their state fits in the device arena."""
+    (pt_server).  Jobs wait until their state fits in the device arena.  The
+    launch stays resident until stop(): do not call torch.cuda.synchronize()
+    (a device-wide wait) while a server runs."""
 
     def __init__(self, arena_bytes=1 << 30, max_jobs=8192, precision=PREC_F64, threads=0, lds_budget=0):
         self._lib = load_library()
