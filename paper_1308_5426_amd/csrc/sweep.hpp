@@ -643,6 +643,41 @@ __device__ __forceinline__ double dE_now(const Walker<F> &W, int L, int a, int b
     return dE;
 }
 
+// Direct energy changes (no field table): dE of every lane's attempt,
+// sum_j J*(|i-j|) ([s_j = a] - [s_j = b]), over the spins in LDS (current: the
+// chain writes each committed flip's spin at once), in FP64.  The 64 sums
+// are split between the waves, each wave taking a contiguous share of the
+// attempts with all its lanes running over the sites, and exchanged through
+// LDS (one barrier); every wave ends with the same 64 values.
+template <typename F>
+__device__ __forceinline__ double direct_dE_window(const Walker<F> &W, int L, int i, int a, int b, int &pbuf)
+{
+    const int nw = blockDim.x / kWave, wv = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    const int per = (kWave + nw - 1) / nw;
+    const int g0 = wv * per, g1 = min(kWave, g0 + per);
+    double mine = 0.0;
+    for (int g = g0; g < g1; ++g) {
+        const int ig = rl_i(i, g), ag = rl_i(a, g), bg = rl_i(b, g);
+        double part = 0.0;
+        for (int j = lane; j < L; j += kWave) {
+            const int s = W.sp[j];
+            int d = j - ig;
+            d += d < 0 ? L : 0;
+            const double jv = W.J64[d];
+            part += s == ag ? jv : (s == bg ? -jv : 0.0);
+        }
+        const double tot = wave_sum(part);
+        mine = lane == g ? tot : mine;
+    }
+    if (nw == 1) return mine;
+    double *xp = W.xpart + pbuf * nw * kWave;
+    if (lane >= g0 && lane < g1) xp[lane] = mine;
+    __syncthreads();
+    const double r = xp[lane];
+    pbuf ^= 1;
+    return r;
+}
+
 // The chain through attempts [t0, t0 + 64) (lanes past `cend` idle), run by
 // every wave of the workgroup on the same 64 attempts: all decisions are taken
 // identically in each wave, the long correction passes are split between the
@@ -671,7 +706,7 @@ __device__ __forceinline__ double dE_now(const Walker<F> &W, int L, int a, int b
 // flip, so Bd = 2 (init + nupd * unit) grown by 2 unit per flip bounds its
 // error exactly as for two separately kept fields; a split pass adds `ex`
 // more such units per lane.
-template <typename F, bool D>
+template <typename F, bool D, bool DIR>
 __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w, int64_t n, double beta, int t0,
                                              int c0, int cend, ChainRegs &cr, int &pbuf)
 {
@@ -689,7 +724,11 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
     int a = W.sp[i];
     int b = a + kk;
     b -= b >= q ? q : 0;
-    double dE = static_cast<double>(W.h[a * L + i]) - static_cast<double>(W.h[b * L + i]);
+    double dE;
+    if constexpr (DIR)
+        dE = direct_dE_window(W, L, i, a, b, pbuf);
+    else
+        dE = static_cast<double>(W.h[a * L + i]) - static_cast<double>(W.h[b * L + i]);
     uint32_t code = state_code(a, b);
     int ex = 0;  // extra roundings in this lane's dE, in units of 2 unit
     uint64_t live = ballot(valid);
@@ -742,14 +781,14 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
         if (lead && ((C >> lane) & 1ull)) {
             atomicAdd(&W.cnt[a], -1);
             atomicAdd(&W.cnt[b], 1);
-            if (kF64) {  // FP32 tables take E from the flush's exact sums
+            if (kF64 || DIR) {  // FP32 tables take E from the flush's exact sums
                 cr.eL += dE;
                 cr.errL += Bdl;
             }
         }
         const int nc = __popcll(C);
         np += nc;
-        cr.nupd += nc;
+        if (!DIR) cr.nupd += nc;  // flips the table will take (none without a table)
         cr.nacc += nc;
         Bd += static_cast<double>(nc) * dBd;
         if (V) {
@@ -785,13 +824,13 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
                 if (lead && lane == m) {
                     atomicAdd(&W.cnt[a_m], -1);
                     atomicAdd(&W.cnt[b_m], 1);
-                    if (kF64) {
+                    if (kF64 || DIR) {
                         cr.eL += dEm;
                         cr.errL += errm;
                     }
                 }
                 ++np;
-                ++cr.nupd;
+                if (!DIR) ++cr.nupd;
                 ++cr.nacc;
                 Bd += dBd;
                 const int c = dE_coef(lane > m ? code : 0u, pk_m);
@@ -807,8 +846,19 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
         if (ballot(redo)) {
             int b2 = sn + kk;
             b2 -= b2 >= q ? q : 0;
-            int ex2;
-            const double dE2 = dE_now<F, D>(W, L, redo ? sn : a, redo ? b2 : b, i, np, ex2, pbuf);
+            int ex2 = 0;
+            double dE2;
+            if constexpr (DIR) {
+                // direct sums for the lanes that need them, one by one, in every wave alike
+                dE2 = 0.0;
+                for (uint64_t rm = ballot(redo); rm; rm &= rm - 1ull) {
+                    const int g = static_cast<int>(__builtin_ctzll(rm));
+                    const double t = chain_direct_dE(W, L, rl_i(i, g), rl_i(sn, g), rl_i(b2, g));
+                    dE2 = lane == g ? t : dE2;
+                }
+            } else {
+                dE2 = dE_now<F, D>(W, L, redo ? sn : a, redo ? b2 : b, i, np, ex2, pbuf);
+            }
             if (redo) {
                 a = sn;
                 b = b2;
@@ -963,7 +1013,9 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
 }
 
 // One sweep of walker w at sweep index n.  Returns this thread's part of the
-// exact energy change (FP32 table; zero otherwise).  D: doubled coupling row.
+// exact energy change (FP32 table; zero otherwise).  D: the field table is in
+// LDS (with a doubled coupling row); otherwise the chain takes its energy
+// changes from direct sums over the spins and there is no table to update.
 template <typename F, int QT, bool D>
 __device__ __forceinline__ double sweep_walker(const Inst &P, Walker<F> &W, int w, int64_t n, double beta, ChainRegs &cr)
 {
@@ -975,10 +1027,10 @@ __device__ __forceinline__ double sweep_walker(const Inst &P, Walker<F> &W, int 
         gen_draws<F>(P, W, w, n, c0, cend - c0);
         __syncthreads();
         for (int t0 = c0; t0 < cend; t0 += kWave) {
-            chain_window<F, D>(P, W, w, n, beta, t0, c0, cend, cr, pbuf);
+            chain_window<F, D, !D>(P, W, w, n, beta, t0, c0, cend, cr, pbuf);
             __syncthreads();
             const int np = W.cs->np[(t0 / kWave) & 1];
-            if (np > 0) {
+            if (D && np > 0) {  // without a table in LDS the chain works from direct sums: nothing to flush
                 flush_window<F, QT, D>(P, W, np, part);
                 __syncthreads();
             }
@@ -1054,8 +1106,9 @@ __device__ __forceinline__ bool run_walker(const Inst &P, const LdsPlan &plan, u
         const double beta = P.beta[slot];
         cr.nacc = 0;
         const double part = sweep_walker<F, QT, HLDS>(P, W, w, n, beta, cr);
-        // energy change of the sweep: the flush's exact sums (FP32 table) or
-        // the accepted flips' dE held by the chain lanes (FP64 table)
+        // energy change of the sweep: the flush's exact sums (FP32 table in
+        // LDS) or the accepted flips' dE held by the chain lanes (FP64 table,
+        // or direct sums when there is no table in LDS)
         cr.E += block_sum(part + cr.eL, W.red);
         cr.Eerr += block_sum(cr.errL, W.red);
         cr.eL = cr.errL = 0.0;
@@ -1067,7 +1120,8 @@ __device__ __forceinline__ bool run_walker(const Inst &P, const LdsPlan &plan, u
         cr.nupd = W.cs->nupd;
         cr.nacc = W.cs->nacc;
         record_sweep<F>(P, W, w, slot, n, cr.E, cr.nacc);
-        if ((P.refresh_every > 0 && (n + 1) % P.refresh_every == 0) || cr.nupd > P.nupd_max) {
+        // without a table in LDS there is nothing to refresh (energies come from direct sums)
+        if (HLDS && ((P.refresh_every > 0 && (n + 1) % P.refresh_every == 0) || cr.nupd > P.nupd_max)) {
             cr.E = refresh_fields<F>(P, W);
             cr.Eerr = 0.0;
             cr.nupd = 0;
