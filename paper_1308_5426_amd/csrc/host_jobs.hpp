@@ -98,8 +98,8 @@ pt_status shape_defaults(const pt_options &o, int prec, int *threads, int *budge
     HIPCHK(hipFuncGetAttributes(&fa, jobs_fn_prec(prec)));
     const int cap = (lds_max - static_cast<int>(fa.sharedSizeBytes)) & ~255;
     *budget = std::min(cap, o.lds_budget > 0 ? o.lds_budget : 64 * 1024);
-    if (*threads % kWave || *threads < kWave || *threads > kMaxSweepThreads)
-        return fail(PT_EINVAL, "threads must be a multiple of 64 in [64, %d]", kMaxSweepThreads);
+    if (*threads % kWave || *threads < kWave || *threads > kMaxJobThreads)
+        return fail(PT_EINVAL, "threads must be a multiple of 64 in [64, %d]", kMaxJobThreads);
     if (*budget < 4096) return fail(PT_EINVAL, "lds_budget must be at least 4096 B");
     return PT_OK;
 }

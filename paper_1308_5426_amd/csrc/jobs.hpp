@@ -152,7 +152,7 @@ __device__ __forceinline__ void dispatch_job_walker(const JobSlot &S, int w, uns
 // memory) counts the valid slots, *stop (host memory) ends the launch once no
 // published ticket is left.
 template <typename F>
-__global__ __launch_bounds__(kMaxSweepThreads) void k_jobs(const JobSlot *__restrict__ slots, int32_t nstatic,
+__global__ __launch_bounds__(kMaxJobThreads) void k_jobs(const JobSlot *__restrict__ slots, int32_t nstatic,
                                                            const int32_t *published, const int32_t *stop,
                                                            JobControl *ctl, int32_t *done_flags)
 {

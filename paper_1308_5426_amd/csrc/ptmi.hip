@@ -69,6 +69,7 @@ namespace {
 
 size_t field_bytes(int prec) { return prec == PT_PREC_F32 ? sizeof(float) : sizeof(double); }
 
+// One wave per 256 sites, up to one wave per SIMD.
 int auto_threads(int L)
 {
     const int waves = std::min(kMaxSweepThreads / kWave, std::max(1, (L + 255) / 256));
@@ -166,9 +167,9 @@ pt_status validate(int32_t L, int32_t q, double sigma, const double *T, int32_t 
     return PT_OK;
 }
 
-// Kernel variant by the number of states (flush fields in registers for up to
-// 4 states, direct LDS updates beyond) and by where the field table and the
-// FP64 couplings live.
+// Kernel variant by the number of states (four flush rows in registers for
+// q <= 4; row by row beyond) and by where the field table and the FP64
+// couplings live.
 template <typename F, bool HLDS, bool J64L>
 const void *sweep_fn_q(int q)
 {

@@ -57,8 +57,9 @@ struct ChainState {
 // (FP64 rounding of the products and of the library logarithm).
 constexpr double kEvalMargin = 1e-12;
 // Workgroup size limit of the walker kernels: one wave per SIMD, so every wave
-// may use the whole register file (per-lane fields of up to 16 states).
+// may use the whole register file.
 constexpr int kMaxSweepThreads = 256;
+constexpr int kMaxJobThreads = 256;
 // Grid barrier time-out, in wall-clock ticks (100 MHz on gfx9): 20 s.
 constexpr uint64_t kBarrierTicks = 2000000000ull;
 
@@ -894,12 +895,15 @@ template <typename F, int QT, bool D>
 __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np, double &part)
 {
     constexpr int QR = QT > 0 ? QT : 1;  // rows held in registers (q <= 4)
-    constexpr int M = kFlushM;
+    constexpr int M = kFlushM;             // register slots per thread
     constexpr int B = kFlipBatch;
     constexpr bool kF32 = sizeof(F) == sizeof(float);
     const int L = P.L, q = P.q, tid = threadIdx.x, NT = blockDim.x, lane = tid & (kWave - 1);
+    // sites per thread and pass: 4 up to 256 threads, 2 at 512 (wave-uniform)
+    const int Me = NT > 256 ? 2 : M;
+    const bool full = Me > 2;  // slots 2 and 3 in use
     const uint32_t pv = lane < np ? W.pend[lane] : kNoFlip;  // the chain already wrote the spins
-    for (int jb = (tid / kWave) * kWave * M; jb < L; jb += NT * M) {
+    for (int jb = (tid / kWave) * kWave * Me; jb < L; jb += NT * Me) {
         const int j0 = jb + lane;
         int jm[M];
         bool ok[M];
@@ -908,7 +912,7 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             const int j = j0 + m * kWave;
-            ok[m] = j < L;
+            ok[m] = m < Me && j < L;
             jm[m] = ok[m] ? j : 0;
             sr[m] = (kF32 && ok[m]) ? W.sp[j] : -1;
         }
@@ -939,11 +943,16 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
                 for (int m = 0; m < M; ++m) {
                     int d = jm[m] - ip;
                     d += d < 0 ? L : 0;
-                    if constexpr (D)
-                        g[e][m] = Jrow[m * kWave - ip];
-                    else
-                        g[e][m] = W.J[d];
-                    g64[e][m] = kF32 ? W.J64[d] : 0.0;
+                    if (m < 2 || full) {
+                        if constexpr (D)
+                            g[e][m] = Jrow[m * kWave - ip];
+                        else
+                            g[e][m] = W.J[d];
+                        g64[e][m] = kF32 ? W.J64[d] : 0.0;
+                    } else {
+                        g[e][m] = F(0);
+                        g64[e][m] = 0.0;
+                    }
                 }
             }
 #pragma unroll
@@ -957,7 +966,8 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
                     for (int c = 0; c < QT; ++c) {
                         const F k = kc[c];
 #pragma unroll
-                        for (int m = 0; m < M; ++m) hr[c][m] = fma(k, g[e][m], hr[c][m]);
+                        for (int m = 0; m < M; ++m)
+                            if (m < 2 || full) hr[c][m] = fma(k, g[e][m], hr[c][m]);
                     }
                 }
                 if (kF32) {

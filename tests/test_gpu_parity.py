@@ -142,7 +142,8 @@ def test_fused_equals_unfused(pkg, orc, precision):
 
 
 @pytest.mark.parametrize("L,q,threads", [(100, 2, 64), (1000, 5, 256), (1000, 5, 192), (1000, 5, 64),
-                                         (257, 16, 128), (2, 2, 64), (3, 3, 64)])
+                                         (257, 16, 128), (2, 2, 64), (3, 3, 64), (1000, 3, 256),
+                                         (1000, 4, 128), (100, 3, 64), (2500, 3, 256)])
 def test_tiles_and_ragged_sizes(pkg, orc, L, q, threads):
     T = _ladder(0.2, 3.0, 6)
     run_pair(pkg, orc, L, q, 0.45, T, 99, 20, 1, threads=threads, steps=2, mode=1 if L >= 1000 else 0)
