@@ -43,7 +43,7 @@ struct LdsPlan {
 // jb + v * 64 * kFlushM + 64 m + l, m < kFlushM.
 constexpr int kFlushM = 4;
 // Flips whose couplings are gathered together before they are applied.
-constexpr int kFlipBatch = 8;
+constexpr int kFlipBatch = 4;
 
 // Scalars of the walker's chain, kept by wave 0 and published through LDS.
 struct ChainState {
