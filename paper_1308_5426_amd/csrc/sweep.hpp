@@ -899,11 +899,9 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
     constexpr int B = kFlipBatch;
     constexpr bool kF32 = sizeof(F) == sizeof(float);
     const int L = P.L, q = P.q, tid = threadIdx.x, NT = blockDim.x, lane = tid & (kWave - 1);
-    // sites per thread and pass: 4 up to 256 threads, 2 at 512 (wave-uniform)
-    const int Me = NT > 256 ? 2 : M;
-    const bool full = Me > 2;  // slots 2 and 3 in use
+    static_assert(kMaxSweepThreads <= 256 && kMaxJobThreads <= 256, "M sites per thread assume <= 256 threads");
     const uint32_t pv = lane < np ? W.pend[lane] : kNoFlip;  // the chain already wrote the spins
-    for (int jb = (tid / kWave) * kWave * Me; jb < L; jb += NT * Me) {
+    for (int jb = (tid / kWave) * kWave * M; jb < L; jb += NT * M) {
         const int j0 = jb + lane;
         int jm[M];
         bool ok[M];
@@ -912,7 +910,7 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             const int j = j0 + m * kWave;
-            ok[m] = m < Me && j < L;
+            ok[m] = j < L;
             jm[m] = ok[m] ? j : 0;
             sr[m] = (kF32 && ok[m]) ? W.sp[j] : -1;
         }
@@ -943,16 +941,11 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
                 for (int m = 0; m < M; ++m) {
                     int d = jm[m] - ip;
                     d += d < 0 ? L : 0;
-                    if (m < 2 || full) {
-                        if constexpr (D)
-                            g[e][m] = Jrow[m * kWave - ip];
-                        else
-                            g[e][m] = W.J[d];
-                        g64[e][m] = kF32 ? W.J64[d] : 0.0;
-                    } else {
-                        g[e][m] = F(0);
-                        g64[e][m] = 0.0;
-                    }
+                    if constexpr (D)
+                        g[e][m] = Jrow[m * kWave - ip];
+                    else
+                        g[e][m] = W.J[d];
+                    g64[e][m] = kF32 ? W.J64[d] : 0.0;
                 }
             }
 #pragma unroll
@@ -967,7 +960,7 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
                         const F k = kc[c];
 #pragma unroll
                         for (int m = 0; m < M; ++m)
-                            if (m < 2 || full) hr[c][m] = fma(k, g[e][m], hr[c][m]);
+                            hr[c][m] = fma(k, g[e][m], hr[c][m]);
                     }
                 }
                 if (kF32) {
