@@ -71,13 +71,14 @@ pt_status jobs_capacity(int prec, int threads, int budget, int *cap)
 }
 
 void job_slot(JobSlot &S, const pt_job_desc &j, int prec, unsigned char *base, const double *Tdev,
-              const LdsPlan &plan, int32_t variant, int32_t wbase)
+              const LdsPlan &plan, int32_t variant, int32_t wbase, unsigned long long *jc)
 {
     const Layout lay = layout_of(j.L, j.q, j.R, prec, 0, kJobEvents);
     std::memset(&S, 0, sizeof S);
     fill_inst(S.inst, base, lay, j.L, j.q, j.R, j.seed, prec == PT_PREC_F32 ? 32 : 0, 0, kJobEvents);
     S.plan = plan;
     S.T = Tdev;
+    S.jc = jc;
     S.sigma = j.sigma;
     S.sweeps = j.sweeps;
     S.xevery = j.exchange_every;
@@ -132,9 +133,10 @@ struct pt_batch {
     std::vector<pt_job_desc> jobs;
     JobSlot *d_slots = nullptr;
     JobControl *d_ctl = nullptr;
+    unsigned long long *d_jc = nullptr;  // [njobs][2] ready / finished words
     double *d_T = nullptr;
     std::vector<double> Tall;
-    size_t slots_off = 0, ctl_off = 0, T_off = 0, total = 0;
+    size_t slots_off = 0, ctl_off = 0, jc_off = 0, T_off = 0, total = 0;
     std::vector<size_t> job_off;
 };
 
@@ -157,6 +159,8 @@ pt_status batch_layout(const pt_job_desc *jobs, int32_t n, const pt_options &o, 
     off += Layout::up(sizeof(JobSlot) * n);
     b->ctl_off = off;
     off += Layout::up(sizeof(JobControl));
+    b->jc_off = off;
+    off += Layout::up(sizeof(unsigned long long) * 2 * static_cast<size_t>(n));
     b->T_off = off;
     off += Layout::up(sizeof(double) * nT);
     b->total = off;
@@ -227,6 +231,7 @@ pt_status pt_batch_create(pt_batch **out, const pt_job_desc *jobs, int32_t njobs
     }
     b->d_slots = reinterpret_cast<JobSlot *>(b->ws + b->slots_off);
     b->d_ctl = reinterpret_cast<JobControl *>(b->ws + b->ctl_off);
+    b->d_jc = reinterpret_cast<unsigned long long *>(b->ws + b->jc_off);
     b->d_T = reinterpret_cast<double *>(b->ws + b->T_off);
     b->slots.resize(njobs);
     b->jobs.assign(jobs, jobs + njobs);
@@ -237,7 +242,8 @@ pt_status pt_batch_create(pt_batch **out, const pt_job_desc *jobs, int32_t njobs
         int32_t variant = 0;
         if ((st = job_plan(jobs[j], b->prec, b->budget, b->threads, &plan, &variant)) != PT_OK) return bail(st);
         b->Tall.insert(b->Tall.end(), jobs[j].T, jobs[j].T + jobs[j].R);
-        job_slot(b->slots[j], jobs[j], b->prec, b->ws + b->job_off[j], b->d_T + toff, plan, variant, wbase);
+        job_slot(b->slots[j], jobs[j], b->prec, b->ws + b->job_off[j], b->d_T + toff, plan, variant, wbase,
+                 b->d_jc + 2 * static_cast<size_t>(j));
         b->jobs[j].T = nullptr;
         toff += jobs[j].R;
         wbase += jobs[j].R;
@@ -257,7 +263,7 @@ pt_status pt_batch_run(pt_batch *b)
     if (!b) return fail(PT_EINVAL, "null batch");
     if (b->ran) return fail(PT_ESTATE, "batch already ran");
     HIPCHK(hipMemsetAsync(b->ws, 0, b->slots_off, b->stream));
-    HIPCHK(hipMemsetAsync(b->d_ctl, 0, sizeof(JobControl), b->stream));
+    HIPCHK(hipMemsetAsync(b->d_ctl, 0, b->T_off - b->ctl_off, b->stream));  // ticket and ready/finished words
     HIPCHK(hipMemcpyAsync(b->d_slots, b->slots.data(), sizeof(JobSlot) * b->njobs, hipMemcpyHostToDevice, b->stream));
     HIPCHK(hipMemcpyAsync(b->d_T, b->Tall.data(), sizeof(double) * b->Tall.size(), hipMemcpyHostToDevice, b->stream));
     const JobSlot *slots = b->d_slots;
@@ -331,17 +337,15 @@ struct ServerJob {
 struct pt_server {
     int32_t prec = 0, threads = 128, budget = 0, grid = 0, max_jobs = 0;
     size_t arena_bytes = 0;
-    unsigned char *mem = nullptr;   // device: arena | slots | control | temperatures
+    unsigned char *mem = nullptr;   // device: arena | control | ready/finished words
     bool own_mem = false;
-    size_t slots_off = 0, ctl_off = 0, T_off = 0;
-    JobSlot *d_slots = nullptr;
+    size_t ctl_off = 0, jc_off = 0;
     JobControl *d_ctl = nullptr;
-    double *d_T = nullptr;          // [max_jobs][64] temperatures
+    unsigned long long *d_jc = nullptr;  // [max_jobs][2]
     int32_t *h_ctl = nullptr;       // pinned: [0] published, [1] stop
     int32_t *h_done = nullptr;      // pinned: [max_jobs]
-    JobSlot *h_slot = nullptr;      // pinned staging for one slot
-    double *h_T = nullptr;          // pinned staging for one ladder
-    unsigned long long *h_zero = nullptr;
+    JobSlot *h_slots = nullptr;     // pinned: [max_jobs] job table read by the running kernel
+    double *h_T = nullptr;          // pinned: [max_jobs][64] temperatures
     hipStream_t kstream = nullptr, cstream = nullptr;
     std::mutex mu;
     std::condition_variable cv;
@@ -395,7 +399,7 @@ void arena_free(pt_server *s, size_t off, size_t bytes)
 }
 
 // Admit the queue's head jobs that fit, in order; publish them.
-bool server_admit(pt_server *s, std::unique_lock<std::mutex> &lk)
+bool server_admit(pt_server *s)
 {
     bool any = false;
     while (!s->queue.empty() && s->published < s->max_jobs) {
@@ -408,24 +412,12 @@ bool server_admit(pt_server *s, std::unique_lock<std::mutex> &lk)
         LdsPlan plan;
         int32_t variant = 0;
         job_plan(J.desc, s->prec, s->budget, s->threads, &plan, &variant);
-        const double *Tdev = s->d_T + static_cast<size_t>(J.slot) * kServerMaxR;
-        job_slot(*s->h_slot, J.desc, s->prec, s->mem + off, Tdev, plan, variant, s->wbase);
-        std::memcpy(s->h_T, J.T.data(), sizeof(double) * J.desc.R);
-        lk.unlock();
-        const Inst &P = s->h_slot->inst;
-        bool ok = hipMemcpyAsync(P.ctr, s->h_zero, sizeof(unsigned long long) * kCtrN, hipMemcpyHostToDevice,
-                                 s->cstream) == hipSuccess &&
-                  hipMemcpyAsync(const_cast<double *>(Tdev), s->h_T, sizeof(double) * J.desc.R,
-                                 hipMemcpyHostToDevice, s->cstream) == hipSuccess &&
-                  hipMemcpyAsync(s->d_slots + J.slot, s->h_slot, sizeof(JobSlot), hipMemcpyHostToDevice,
-                                 s->cstream) == hipSuccess &&
-                  hipStreamSynchronize(s->cstream) == hipSuccess;
-        lk.lock();
-        if (!ok) {
-            s->failed = true;
-            s->fail_msg = "copy to the device failed";
-            return any;
-        }
+        // the slot and ladder go straight into pinned host memory, before the
+        // published count that makes them visible to the kernel
+        double *Th = s->h_T + static_cast<size_t>(J.slot) * kServerMaxR;
+        std::memcpy(Th, J.T.data(), sizeof(double) * J.desc.R);
+        job_slot(s->h_slots[J.slot], J.desc, s->prec, s->mem + off, Th, plan, variant, s->wbase,
+                 s->d_jc + 2 * static_cast<size_t>(J.slot));
         s->wbase += J.desc.R;
         s->published += 1;
         J.state = 1;
@@ -470,7 +462,7 @@ void server_loop(pt_server *s)
 {
     std::unique_lock<std::mutex> lk(s->mu);
     while (!s->failed) {
-        const bool a = server_admit(s, lk);
+        const bool a = server_admit(s);
         const bool c = server_collect(s, lk);
         if (a || c) s->cv.notify_all();
         if (s->quit && s->queue.empty() && s->running.empty()) break;
@@ -500,9 +492,8 @@ pt_status pt_server_start(pt_server **out, size_t arena_bytes, int32_t max_jobs,
         if (s->own_mem && s->mem) (void)hipFree(s->mem);
         if (s->h_ctl) (void)hipHostFree(s->h_ctl);
         if (s->h_done) (void)hipHostFree(s->h_done);
-        if (s->h_slot) (void)hipHostFree(s->h_slot);
+        if (s->h_slots) (void)hipHostFree(s->h_slots);
         if (s->h_T) (void)hipHostFree(s->h_T);
-        if (s->h_zero) (void)hipHostFree(s->h_zero);
         delete s;
         return st;
     };
@@ -511,10 +502,9 @@ pt_status pt_server_start(pt_server **out, size_t arena_bytes, int32_t max_jobs,
     pt_status st0 = shape_defaults(o, s->prec, &s->threads, &s->budget);
     if (st0 != PT_OK) return bail(st0);
     s->arena_bytes = Layout::up(arena_bytes);
-    s->slots_off = s->arena_bytes;
-    s->ctl_off = s->slots_off + Layout::up(sizeof(JobSlot) * static_cast<size_t>(max_jobs));
-    s->T_off = s->ctl_off + Layout::up(sizeof(JobControl));
-    const size_t total = s->T_off + Layout::up(sizeof(double) * kServerMaxR * static_cast<size_t>(max_jobs));
+    s->ctl_off = s->arena_bytes;
+    s->jc_off = s->ctl_off + Layout::up(sizeof(JobControl));
+    const size_t total = s->jc_off + Layout::up(sizeof(unsigned long long) * 2 * static_cast<size_t>(max_jobs));
     if (o.workspace) {
         if (o.workspace_bytes < total) return bail(fail(PT_ENOMEM, "workspace of %zu B < %zu B", o.workspace_bytes, total));
         s->mem = static_cast<unsigned char *>(o.workspace);
@@ -522,18 +512,16 @@ pt_status pt_server_start(pt_server **out, size_t arena_bytes, int32_t max_jobs,
         if (hipMalloc(&s->mem, total) != hipSuccess) return bail(fail(PT_ENOMEM, "hipMalloc(%zu) failed", total));
         s->own_mem = true;
     }
-    s->d_slots = reinterpret_cast<JobSlot *>(s->mem + s->slots_off);
     s->d_ctl = reinterpret_cast<JobControl *>(s->mem + s->ctl_off);
-    s->d_T = reinterpret_cast<double *>(s->mem + s->T_off);
+    s->d_jc = reinterpret_cast<unsigned long long *>(s->mem + s->jc_off);
     if (hipHostMalloc(&s->h_ctl, 256, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(&s->h_done, sizeof(int32_t) * max_jobs, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc(&s->h_slot, sizeof(JobSlot), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc(&s->h_T, sizeof(double) * kServerMaxR, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc(&s->h_zero, sizeof(unsigned long long) * kCtrN, hipHostMallocDefault) != hipSuccess)
+        hipHostMalloc(&s->h_slots, sizeof(JobSlot) * max_jobs, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&s->h_T, sizeof(double) * kServerMaxR * max_jobs, hipHostMallocDefault) != hipSuccess)
         return bail(fail(PT_ENOMEM, "pinned host allocation failed"));
     std::memset(s->h_ctl, 0, 256);
     std::memset(s->h_done, 0, sizeof(int32_t) * max_jobs);
-    std::memset(s->h_zero, 0, sizeof(unsigned long long) * kCtrN);
+    std::memset(static_cast<void *>(s->h_slots), 0, sizeof(JobSlot) * max_jobs);
     if (hipStreamCreateWithFlags(&s->kstream, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&s->cstream, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(PT_EDEVICE, "stream creation failed"));
@@ -543,9 +531,10 @@ pt_status pt_server_start(pt_server **out, size_t arena_bytes, int32_t max_jobs,
     if (cap < kServerMaxR) return bail(fail(PT_EINVAL, "only %d workgroups fit at once (need %d)", cap, kServerMaxR));
     s->grid = cap;
     s->free_blocks[0] = s->arena_bytes;
-    if (hipMemsetAsync(s->d_ctl, 0, sizeof(JobControl), s->kstream) != hipSuccess)
+    // ticket and every slot's ready/finished words start at zero with the launch
+    if (hipMemsetAsync(s->d_ctl, 0, total - s->ctl_off, s->kstream) != hipSuccess)
         return bail(fail(PT_EDEVICE, "memset failed"));
-    const JobSlot *slots = s->d_slots;
+    const JobSlot *slots = s->h_slots;
     int32_t nstatic = -1;
     const int32_t *pub = s->h_ctl, *stop = s->h_ctl + 1;
     JobControl *ctl = s->d_ctl;
@@ -667,9 +656,8 @@ pt_status pt_server_stop(pt_server *s)
     if (s->own_mem && s->mem) (void)hipFree(s->mem);
     (void)hipHostFree(s->h_ctl);
     (void)hipHostFree(s->h_done);
-    (void)hipHostFree(s->h_slot);
+    (void)hipHostFree(s->h_slots);
     (void)hipHostFree(s->h_T);
-    (void)hipHostFree(s->h_zero);
     delete s;
     if (e != hipSuccess) return fail(PT_EDEVICE, "server kernel: %s", hipGetErrorString(e));
     if (failed) return fail(PT_EDEVICE, "server failed");

@@ -7,12 +7,21 @@
 // the rest.  With at least max_j R_j workgroups resident, the per-job device
 // barriers therefore always fill and the launch cannot deadlock.
 //
-// A claimed walker sets up its own state: walker 0 computes the job's
-// couplings (eq. 6) and publishes them; every walker draws its initial spins,
-// builds its field table and runs the job's sweeps with the exchange after
-// each (the same code as a single instance).  The last walker to finish marks
-// the job done.  A static batch has a fixed job count; a server keeps
-// publishing jobs (the count lives in host-visible memory) until told to stop.
+// A claimed walker sets up its own state: walker 0 clears the job's counters,
+// computes its couplings (eq. 6) and publishes them; every walker draws its
+// initial spins, builds its field table and runs the job's sweeps with the
+// exchange after each (the same code as a single instance).  The last walker
+// to finish marks the job done; a walker that gave up (barrier time-out) still
+// counts, with an error bit, so a failed job ends instead of hanging.
+//
+// A static batch has a fixed job count and its table in device memory,
+// written before the launch.  A server keeps publishing jobs while the launch
+// runs: its job table and ladders live in pinned host memory, written by the
+// host before it raises the published count (host memory is coherent with the
+// device, unlike host copies into device memory during a launch).  Nothing the
+// device reads of a job comes from such a copy: the ready/finished words are one
+// pair per slot, never reused and cleared before the launch, and the counters
+// in the job's (reused) arena block are cleared by the device itself.
 #pragma once
 #include "sweep.hpp"
 
@@ -23,7 +32,8 @@ enum : int32_t { kVarHLds = 1, kVarJ64Lds = 2, kVarRegFlush = 4 };
 struct alignas(256) JobSlot {
     Inst inst;
     LdsPlan plan;      // carve of this job inside the launch's LDS budget
-    const double *T;   // [R] ascending temperatures (device memory)
+    const double *T;   // [R] ascending temperatures (device or pinned host memory)
+    unsigned long long *jc;  // [2] couplings ready, walkers finished (device memory, zero at launch)
     double sigma;
     int64_t sweeps;
     int32_t xevery;
@@ -47,9 +57,12 @@ template <typename F, int QT, bool HLDS, bool J64L>
 __device__ __forceinline__ void run_job_walker(const JobSlot &S, int w, unsigned char *lds, int32_t *done_flag, int32_t *sflag)
 {
     Inst P = S.inst;
+    unsigned long long *const jc = S.jc;
     const int tid = threadIdx.x, L = P.L, R = P.R;
     if (w == 0) {
-        // the job's couplings, error bounds, ladder and zeroed accumulators
+        // the job's counters (the arena block may have held an earlier job),
+        // couplings, error bounds, ladder and zeroed accumulators
+        for (int k = tid; k < kCtrN; k += blockDim.x) P.ctr[k] = 0ull;
         double part = 0.0;
         for (int r = tid; r <= L / 2; r += blockDim.x) {
             jstar_entry(L, S.sigma, r, const_cast<double *>(P.J64), const_cast<float *>(P.J32));
@@ -67,16 +80,15 @@ __device__ __forceinline__ void run_job_walker(const JobSlot &S, int w, unsigned
         if (tid == 0) {
             *P.bnd = table_bounds(Ssum, P.J64[1], L, sizeof(F) == sizeof(float));
             __threadfence();
-            __hip_atomic_store(&P.ctr[kCtrJobReady], 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&jc[0], 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
     if (tid == 0) {
         int ok = 1;
         const uint64_t t0 = wall_clock64();
-        while (__hip_atomic_load(&P.ctr[kCtrJobReady], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0ull) {
+        while (__hip_atomic_load(&jc[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0ull) {
             __builtin_amdgcn_s_sleep(8);
             if (wall_clock64() - t0 > kBarrierTicks) {
-                atomicOr(&P.ctr[kCtrError], kErrBarrierTimeout);
                 ok = 0;
                 break;
             }
@@ -85,14 +97,14 @@ __device__ __forceinline__ void run_job_walker(const JobSlot &S, int w, unsigned
         sflag[0] = ok;
     }
     __syncthreads();
-    if (!sflag[0]) return;
-    P.bound_init = __hip_atomic_load(&P.bnd->init, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    P.bound_unit = __hip_atomic_load(&P.bnd->unit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    P.nupd_max = __hip_atomic_load(&P.bnd->nupd_max, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (int j = tid; j < L; j += blockDim.x)
-        P.spins[static_cast<size_t>(w) * L + j] = initial_spin(P, w, j, S.init != 0);
-    __syncthreads();
-    {
+    bool ok = sflag[0] != 0;
+    if (ok) {
+        P.bound_init = __hip_atomic_load(&P.bnd->init, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        P.bound_unit = __hip_atomic_load(&P.bnd->unit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        P.nupd_max = __hip_atomic_load(&P.bnd->nupd_max, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int j = tid; j < L; j += blockDim.x)
+            P.spins[static_cast<size_t>(w) * L + j] = initial_spin(P, w, j, S.init != 0);
+        __syncthreads();
         Walker<F> W = carve<F, HLDS, J64L>(lds, S.plan, P, w);
         load_walker<F>(P, W, S.plan, w);
         const double E = refresh_fields<F>(P, W);
@@ -107,14 +119,13 @@ __device__ __forceinline__ void run_job_walker(const JobSlot &S, int w, unsigned
             P.Mw[w] = (static_cast<double>(P.q) * nmax / L - 1.0) / (P.q - 1);
         }
         __syncthreads();
+        ok = run_walker<F, QT, HLDS, J64L>(P, S.plan, lds, w, 0, static_cast<int32_t>(S.sweeps), S.xevery, 0, true);
     }
-    if (!run_walker<F, QT, HLDS, J64L>(P, S.plan, lds, w, 0, static_cast<int32_t>(S.sweeps), S.xevery, 0, true))
-        return;
     if (tid == 0) {
+        if (!ok) atomicOr(&P.ctr[kCtrError], kErrBarrierTimeout);
         __threadfence_system();
-        const unsigned long long d =
-            __hip_atomic_fetch_add(&P.ctr[kCtrJobDone], 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (done_flag && d == static_cast<unsigned long long>(P.R) - 1ull) {
+        const unsigned long long d = __hip_atomic_fetch_add(&jc[1], 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (done_flag && d == static_cast<unsigned long long>(R) - 1ull) {
             __threadfence_system();
             __hip_atomic_store(done_flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
         }
@@ -148,11 +159,11 @@ __device__ __forceinline__ void dispatch_job_walker(const JobSlot &S, int w, uns
 }
 
 // nstatic >= 0: a batch of nstatic jobs (slots in device memory); the launch
-// ends when every ticket is taken.  nstatic < 0: serving; *published (host
-// memory) counts the valid slots, *stop (host memory) ends the launch once no
-// published ticket is left.
+// ends when every ticket is taken.  nstatic < 0: serving; the slots are in
+// pinned host memory, *published (host memory) counts the valid ones, *stop
+// (host memory) ends the launch once no published ticket is left.
 template <typename F>
-__global__ __launch_bounds__(kMaxJobThreads) void k_jobs(const JobSlot *__restrict__ slots, int32_t nstatic,
+__global__ __launch_bounds__(kMaxJobThreads) void k_jobs(const JobSlot *slots, int32_t nstatic,
                                                            const int32_t *published, const int32_t *stop,
                                                            JobControl *ctl, int32_t *done_flags)
 {

@@ -18,8 +18,6 @@ enum Counter : int {
     kCtrError = 6,       // error bits (kErr*)
     kCtrBarCount = 8,    // grid barrier arrivals (uint32 in the low word)
     kCtrBarGen = 9,      // grid barrier generation
-    kCtrJobReady = 10,   // job kernel: couplings and ladder of the job are ready
-    kCtrJobDone = 11,    // job kernel: walkers of the job that finished
     kCtrN = 16
 };
 enum : unsigned long long { kErrBarrierTimeout = 1ull, kErrBadLaunch = 2ull };
