@@ -98,6 +98,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with __graft_entry__.build() "
                           "(hipcc --offload-arch=gfx950); there is no CPU fallback")
+    # PyTorch first: its HIP runtime is then the one the library binds to, so
+    # device memory and streams from PyTorch and the library's calls share it
+    import torch  # noqa: F401
+
     L = ctypes.CDLL(path)
     i32, i64, u64, d = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
     pp = ctypes.POINTER(ctypes.c_void_p)
