@@ -540,13 +540,13 @@ __device__ __forceinline__ int dE_coef(uint32_t code, uint32_t w)
 }
 
 // dE of every lane after the flips lst[begin..end) (lane r of `lst` holds the
-// r-th flip word), in order, each applied only to the lanes after its own
+// r-th flip word; NEG: taken back out instead), in order, each applied only to the lanes after its own
 // (gate: lane > fw_lane): dE = fma(c, J*(|i-ip|), dE) with c in {-2..2}, one
 // rounding per flip.  The list is read at sequential indices, so the words of
 // a batch are fetched independently; couplings are gathered kFlipBatch flips
 // at a time and applied without branches (entries past `end` read as the
 // padding word), so a batch's gathers stay in flight together.
-template <typename F, bool D>
+template <typename F, bool D, bool NEG = false>
 __device__ __forceinline__ void apply_list(const Walker<F> &W, int L, int i, int lane, uint32_t code, uint32_t lst,
                                            int begin, int end, double &dE)
 {
@@ -562,7 +562,7 @@ __device__ __forceinline__ void apply_list(const Walker<F> &W, int L, int i, int
 #pragma unroll
         for (int e = 0; e < kFlipBatch; ++e) {
             const int c = dE_coef(lane > fw_lane(wb[e]) ? code : 0u, wb[e]);  // code 0: no change
-            dE = fma(static_cast<double>(c), static_cast<double>(jb[e]), dE);
+            dE = fma(static_cast<double>(NEG ? -c : c), static_cast<double>(jb[e]), dE);
         }
     }
 }
@@ -590,20 +590,20 @@ constexpr int kSplitMin = 8;
 // every wave.  Rounding of the split form: each partial is a difference of
 // two intermediate dE values (|.| <= 2 S), so the nw - 1 additions of
 // partials and the final addition add at most 2 units of 2 unit, counted in ex.
-template <typename F, bool D>
+template <typename F, bool D, bool NEG = false>
 __device__ __forceinline__ void add_flips_wg(const Walker<F> &W, int L, int i, int lane, uint32_t code, uint32_t lst,
                                              int begin, int end, double &dE, int &ex, int &pbuf)
 {
     const int nw = blockDim.x / kWave, wv = threadIdx.x / kWave;
     const int n = end - begin;
     if (nw == 1 || n < kSplitMin) {
-        apply_list<F, D>(W, L, i, lane, code, lst, begin, end, dE);
+        apply_list<F, D, NEG>(W, L, i, lane, code, lst, begin, end, dE);
         return;
     }
     const int per = (n + nw - 1) / nw;
     const int b0 = min(end, begin + wv * per), b1 = min(end, b0 + per);
     double part = 0.0;
-    apply_list<F, D>(W, L, i, lane, code, lst, b0, b1, part);
+    apply_list<F, D, NEG>(W, L, i, lane, code, lst, b0, b1, part);
     double *xp = W.xpart + pbuf * nw * kWave;
     xp[wv * kWave + lane] = part;
     __syncthreads();
@@ -813,10 +813,20 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
                     }
                 }
             }
-            // rebuild the later lanes' dE from the committed flips (the list's first nc)
-            dE = dE0;
-            ex = ex0;
-            add_flips_wg<F, D>(W, L, i, lane, code, lst, 0, nc, dE, ex, pbuf);
+            // rebuild the later lanes' dE from the committed flips (the list's
+            // first nc): re-add them to dE0, or, when fewer guessed flips lie
+            // past m, take those back out of the guess.  A lane past m then
+            // keeps the roundings of its r - nc removed flips twice (added
+            // and taken out), 2 (r - nc) more units beyond the committed ones.
+            const int ns = __popcll(S);
+            if (nc <= ns - nc) {
+                dE = dE0;
+                ex = ex0;
+                add_flips_wg<F, D>(W, L, i, lane, code, lst, 0, nc, dE, ex, pbuf);
+            } else {
+                add_flips_wg<F, D, true>(W, L, i, lane, code, lst, nc, ns, dE, ex, pbuf);
+                ex += 2 * max(0, r - nc);
+            }
             if (accept) {
                 if (lane == m) {
                     W.pend[np] = pk_m;
