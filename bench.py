@@ -137,7 +137,7 @@ def run_batch(args):
     prec = 1 if args.precision == "f32" else 0
     jd = [dict(L=j.L, q=j.q, sigma=j.sigma, T=j.T, seed=j.seed, sweeps=j.sweeps, exchange_every=1, init=0)
           for j in jobs]
-    threads, lds = (autotune.tune(jd, precision=prec, verbose=True) if args.autotune else (0, 0))
+    threads, lds = (autotune.tune(jd, precision=prec, verbose=True) if args.autotune else (args.threads, args.lds))
     attempts = sum(j.L * j.R * j.sweeps for j in jobs)
     times, shape = [], None
     for it in range(args.warmup + args.steps):

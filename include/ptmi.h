@@ -68,12 +68,13 @@ typedef struct {
                                with FP64 recheck of near-threshold attempts */
     int32_t init;           /* PT_INIT_RANDOM or PT_INIT_ORDERED (all spins 1) */
     int32_t placement;      /* where the field table lives during a sweep */
-    int32_t threads;        /* threads per walker workgroup (multiple of 64, <= 256); 0 = auto */
+    int32_t threads;        /* threads per walker workgroup (multiple of 64, <= 256); 0 = auto
+                               (single instance: 64 per 256 sites, at most 256; batch/server: 256) */
     int32_t refresh_every;  /* sweeps between O(L^2) recomputations of the fields; 0 = auto */
     int32_t series_capacity;/* sweeps of per-slot E and M to keep (0 = none) */
     int32_t event_capacity; /* entries of the banded-event log (0 = 4096) */
     int32_t max_sweeps_per_launch; /* 0 = auto */
-    int32_t lds_budget;     /* batch/server: LDS bytes per walker workgroup (0 = auto) */
+    int32_t lds_budget;     /* batch/server: LDS bytes per walker workgroup (0 = all the device allows) */
     void *stream;           /* hipStream_t to run on, NULL = the null stream */
     void *workspace;        /* optional caller-owned device memory for all state */
     size_t workspace_bytes; /* its size; must be >= pt_workspace_size() */

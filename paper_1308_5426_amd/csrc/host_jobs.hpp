@@ -87,18 +87,20 @@ void job_slot(JobSlot &S, const pt_job_desc &j, int prec, unsigned char *base, c
     S.variant = variant;
 }
 
-// Walker workgroup shape: threads, and LDS bytes per workgroup clamped to what
-// the device allows beside k_jobs' own static LDS.
+// Walker workgroup shape: threads (default 256: four waves, one per SIMD),
+// and LDS bytes per workgroup (default: all the device allows beside k_jobs'
+// own static LDS, so that as many jobs as possible keep their field table in
+// LDS; one walker per CU either way once a budget exceeds half the LDS).
 pt_status shape_defaults(const pt_options &o, int prec, int *threads, int *budget)
 {
-    *threads = o.threads ? o.threads : 128;
+    *threads = o.threads ? o.threads : 256;
     int dev = 0, lds_max = 0;
     hipFuncAttributes fa;
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     HIPCHK(hipFuncGetAttributes(&fa, jobs_fn_prec(prec)));
     const int cap = (lds_max - static_cast<int>(fa.sharedSizeBytes)) & ~255;
-    *budget = std::min(cap, o.lds_budget > 0 ? o.lds_budget : 64 * 1024);
+    *budget = o.lds_budget > 0 ? std::min(cap, o.lds_budget) : cap;
     if (*threads % kWave || *threads < kWave || *threads > kMaxJobThreads)
         return fail(PT_EINVAL, "threads must be a multiple of 64 in [64, %d]", kMaxJobThreads);
     if (*budget < 4096) return fail(PT_EINVAL, "lds_budget must be at least 4096 B");
@@ -124,7 +126,7 @@ pt_status fetch_spins(const Inst &P, hipStream_t st, uint8_t *spins, int32_t *pe
 // Batches
 // ===========================================================================
 struct pt_batch {
-    int32_t njobs = 0, prec = 0, threads = 128, budget = 0, grid = 0;
+    int32_t njobs = 0, prec = 0, threads = 256, budget = 0, grid = 0;
     hipStream_t stream = nullptr;
     unsigned char *ws = nullptr;
     size_t ws_bytes = 0;
@@ -335,7 +337,7 @@ struct ServerJob {
 };
 
 struct pt_server {
-    int32_t prec = 0, threads = 128, budget = 0, grid = 0, max_jobs = 0;
+    int32_t prec = 0, threads = 256, budget = 0, grid = 0, max_jobs = 0;
     size_t arena_bytes = 0;
     unsigned char *mem = nullptr;   // device: arena | control | ready/finished words
     bool own_mem = false;
