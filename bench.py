@@ -104,11 +104,11 @@ def run_gpu(inst, prec, steps, warmup, max_chunk=0):
     return elapsed, t_kernel, obs_last
 
 
-def cpu_baseline(inst, seconds=12.0, mode=0):
-    """The oracle on this host's cores, on the first sweeps of the same workload."""
+def _oracle_rate(inst, seconds, mode, threads):
+    """Attempts/s of the oracle on `threads` host threads over about `seconds`
+    of sweeps 2.. of the workload (sweep 1 sizes the sample)."""
     import oracle
 
-    threads = min(16, os.cpu_count() or 1)
     pt = oracle.PT(inst.L, inst.q, inst.sigma, inst.T, inst.seed, init=inst.init, mode=mode, threads=threads)
     t0 = time.perf_counter()
     pt.run(1, 1)
@@ -118,11 +118,24 @@ def cpu_baseline(inst, seconds=12.0, mode=0):
     pt.run(n, 1)
     dt = time.perf_counter() - t0
     pt.close()
-    rate = inst.L * inst.R * n / dt
+    return inst.L * inst.R * n / dt, n, dt
+
+
+def cpu_baseline(inst, seconds=12.0, mode=0):
+    """The oracle on this host's cores, on the first sweeps of the same workload:
+    the direct O(L) mode on all cores (the reported value), and shorter samples
+    of the same mode on one core and of the FP64 field-table mode on all cores."""
+    threads = min(16, os.cpu_count() or 1)
+    rate, n, dt = _oracle_rate(inst, seconds, mode, threads)
+    one, n1, dt1 = _oracle_rate(inst, seconds / 4, mode, 1)
+    tab, n2, dt2 = _oracle_rate(inst, seconds / 4, 1 - mode, threads)
     what = "direct O(L) energy difference" if mode == 0 else "FP64 field table"
+    other = "FP64 field table" if mode == 0 else "direct O(L) energy difference"
     return {"value": rate, "unit": "attempts/s", "cores": threads, "kind": "oracle",
             "sample": f"sweeps 2..{n + 1} of the same workload ({inst.R} replicas x {inst.L} sites, exchange "
-                      f"after each sweep), oracle mode: {what}, {dt:.1f} s"}
+                      f"after each sweep), oracle mode: {what}, {dt:.1f} s; also {n1} sweeps on 1 core "
+                      f"({dt1:.1f} s) and {n2} sweeps of the {other} mode on {threads} threads ({dt2:.1f} s)",
+            "value_1core": one, "value_other_mode": tab}
 
 
 def run_batch(args):
