@@ -1,7 +1,9 @@
-// lds_probe.hip -- achievable LDS read bandwidth (see include/ptmi_probe.h).
+// lds_probe.hip -- achievable LDS read bandwidth, and the field update alone
+// (see include/ptmi_probe.h).
 #include <hip/hip_runtime.h>
 
 #include "ptmi_probe.h"
+#include "sweep.hpp"  // the sweep kernel's own flush
 
 namespace {
 
@@ -26,7 +28,110 @@ __global__ __launch_bounds__(1024) void k_lds_read(int iters, uint4 *sink)
     if ((acc.x ^ acc.y ^ acc.z ^ acc.w) == 0x12345678u) sink[blockIdx.x] = acc;
 }
 
+constexpr int kReplayThreads = 256;
+
+// The field update alone: a flip sequence applied window by window (64 flips
+// at a time) to an FP64 field table in LDS by the sweep kernel's flush, with
+// its doubled coupling row and coefficient table laid out as the sweep kernel
+// lays them out.  Every workgroup replays the whole sequence on its own copy;
+// workgroup 0 writes its final table.
+__global__ __launch_bounds__(kReplayThreads) void k_flush_replay(int L, int q, int jlen, const double *J,
+                                                                 const double *h0, const uint32_t *words,
+                                                                 int64_t nwords, int reps, double *h_out)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    double *Jl = reinterpret_cast<double *>(lds);  // [jlen]
+    double *hl = Jl + jlen;                        // [q][L]
+    double *ct = hl + static_cast<size_t>(q) * L;  // [256]
+    uint32_t *pend = reinterpret_cast<uint32_t *>(ct + 256);
+    for (int k = threadIdx.x; k < jlen; k += blockDim.x) Jl[k] = J[k % L];
+    for (int e = threadIdx.x; e < q * L; e += blockDim.x) hl[e] = h0[e];
+    for (int e = threadIdx.x; e < 256; e += blockDim.x) ct[e] = ptmi::flip_coef<double>(e & 3, (e >> 2) & 15, (e >> 2) >> 4);
+    __syncthreads();
+    ptmi::Inst P{};
+    P.L = L;
+    P.q = q;
+    ptmi::Walker<double> W{};
+    W.J = Jl;
+    W.h = hl;
+    W.ctab = ct;
+    W.pend = pend;
+    double part = 0.0;  // FP32 tables only
+    for (int r = 0; r < reps; ++r) {
+        for (int64_t p0 = 0; p0 < nwords; p0 += ptmi::kWave) {
+            const int np = static_cast<int>(nwords - p0 < ptmi::kWave ? nwords - p0 : ptmi::kWave);
+            if (threadIdx.x < ptmi::kWave) pend[threadIdx.x] = static_cast<int>(threadIdx.x) < np ? words[p0 + threadIdx.x] : ptmi::kNoFlip;
+            __syncthreads();
+            ptmi::flush_window<double, 4, true>(P, W, np, part);
+            __syncthreads();
+        }
+    }
+    if (blockIdx.x == 0)
+        for (int e = threadIdx.x; e < q * L; e += blockDim.x) h_out[e] = hl[e];
+}
+
 }  // namespace
+
+extern "C" int ptmi_flush_replay(int32_t L, int32_t q, const double *jstar, const double *h0, const uint32_t *words,
+                                 int64_t nwords, int32_t workgroups, int32_t reps, double *h_out, double *ms_out)
+{
+    if (L < 2 || L > 65535 || q < 2 || q > 4 || !jstar || !h0 || (nwords > 0 && !words) || nwords < 0 ||
+        workgroups < 1 || reps < 1 || !h_out || !ms_out)
+        return -1;
+    for (int64_t k = 0; k < nwords; ++k) {  // every word names a site and two states of this table
+        const uint32_t w = words[k];
+        if (static_cast<int>(w & 0xFFFFu) >= L || static_cast<int>((w >> 16) & 15u) >= q ||
+            static_cast<int>((w >> 20) & 15u) >= q)
+            return -1;
+    }
+    const int span = kReplayThreads * ptmi::kFlushM;
+    const int jlen = L + (L + span - 1) / span * span;
+    const size_t lds = sizeof(double) * (static_cast<size_t>(jlen) + static_cast<size_t>(q) * L + 256) +
+                       sizeof(uint32_t) * ptmi::kWave;
+    int dev = 0, lds_max = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return -2;
+    if (lds > static_cast<size_t>(lds_max)) return -1;
+    if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_flush_replay),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
+        return -2;
+    double *dJ = nullptr, *dh0 = nullptr, *dout = nullptr;
+    uint32_t *dw = nullptr;
+    const size_t hb = sizeof(double) * static_cast<size_t>(q) * L;
+    int rc = 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipMalloc(&dJ, sizeof(double) * L) != hipSuccess || hipMalloc(&dh0, hb) != hipSuccess ||
+        hipMalloc(&dout, hb) != hipSuccess || hipMalloc(&dw, sizeof(uint32_t) * (nwords > 0 ? nwords : 1)) != hipSuccess)
+        rc = -3;
+    if (!rc && (hipMemcpy(dJ, jstar, sizeof(double) * L, hipMemcpyHostToDevice) != hipSuccess ||
+                hipMemcpy(dh0, h0, hb, hipMemcpyHostToDevice) != hipSuccess ||
+                (nwords > 0 && hipMemcpy(dw, words, sizeof(uint32_t) * nwords, hipMemcpyHostToDevice) != hipSuccess)))
+        rc = -4;
+    if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) rc = -5;
+    if (!rc) {
+        hipLaunchKernelGGL(k_flush_replay, dim3(workgroups), dim3(kReplayThreads), lds, 0, L, q, jlen, dJ, dh0, dw,
+                           nwords, 1, dout);  // warm-up
+        float ms = 0.f;
+        if (hipEventRecord(e0, 0) != hipSuccess) rc = -6;
+        if (!rc) {
+            hipLaunchKernelGGL(k_flush_replay, dim3(workgroups), dim3(kReplayThreads), lds, 0, L, q, jlen, dJ, dh0,
+                               dw, nwords, reps, dout);
+            if (hipGetLastError() != hipSuccess || hipEventRecord(e1, 0) != hipSuccess ||
+                hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                rc = -6;
+        }
+        if (!rc && hipMemcpy(h_out, dout, hb, hipMemcpyDeviceToHost) != hipSuccess) rc = -7;
+        *ms_out = ms;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(dJ);
+    (void)hipFree(dh0);
+    (void)hipFree(dout);
+    (void)hipFree(dw);
+    return rc;
+}
 
 extern "C" int ptmi_lds_read_bandwidth(int32_t blocks, int32_t threads, int32_t iters, double *bytes_per_s)
 {

@@ -90,3 +90,22 @@ def serve_stream(rate: float = 50.0, duration: float = 60.0, seed: int = SEED):
         out.append((t, Instance(L, q, sigma, geometric_ladder(0.2, 3.0, R), seed + j, sweeps)))
         j += 1
     return out
+
+
+def flip_sequence(L: int, q: int, n: int, seed: int = SEED):
+    """n single-spin flips with the statistics of accepted ones, from all
+    spins in state 0: uniform sites, the old state the site's current one, the
+    new state uniform over the other q - 1.  Returns the words
+    site | old << 16 | new << 20 (states 0-based) and the final spins."""
+    rng = np.random.default_rng(seed)
+    s = np.zeros(L, np.int64)
+    sites = rng.integers(0, L, n)
+    shift = rng.integers(1, q, n) if q > 1 else np.zeros(n, np.int64)
+    words = np.empty(n, np.uint32)
+    for k in range(n):
+        i = sites[k]
+        a = s[i]
+        b = (a + shift[k]) % q
+        words[k] = i | (a << 16) | (b << 20)
+        s[i] = b
+    return words, s
