@@ -39,9 +39,14 @@ def workload(name):
 
 
 def kernel_source_sha():
+    """Hash of the sources libptmi.so is built from (the probe library's own
+    source excluded), so a committed counter summary stays tied to the kernel
+    it measured."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1308_5426_amd", "csrc")
     for f in sorted(os.listdir(d)):
+        if f == "lds_probe.hip":
+            continue
         with open(os.path.join(d, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
@@ -119,6 +124,21 @@ def _oracle_rate(inst, seconds, mode, threads):
     dt = time.perf_counter() - t0
     pt.close()
     return inst.L * inst.R * n / dt, n, dt
+
+
+def field_update_alone(inst, peak, flips=65536, reps=4):
+    """The sweep kernel's flush replayed alone (one workgroup per replica,
+    accept-like flips at the workload's L and q) against the same LDS peak."""
+    import workloads
+    from paper_1308_5426_amd import flush_bench
+
+    words, _ = workloads.flip_sequence(inst.L, inst.q, flips, inst.seed)
+    J = flush_bench.jstar(inst.L, inst.sigma)
+    _, ms = flush_bench.replay(J, inst.q, words, inst.R, reps)
+    achieved = 40.0 * inst.L * flips * reps * inst.R / (ms * 1e-3)
+    return {"kernel": "k_flush_replay (flush_window alone)", "workgroups": inst.R, "flips": flips * reps * inst.R,
+            "ms": ms, "achieved": achieved / 1e9, "unit": "GB/s", "peak": peak / 1e9, "frac": achieved / peak,
+            "frac_occupied_cus": achieved / (peak * min(inst.R, CUS) / CUS)}
 
 
 def cpu_baseline(inst, seconds=12.0, mode=0):
@@ -379,6 +399,8 @@ def main():
             "source_sha": sha,
         },
     }
+    if not prec and inst.q <= 4 and inst.L <= 3000:
+        out["field_update_alone"] = field_update_alone(inst, peak)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds, mode=0)
     print(json.dumps(out), flush=True)
