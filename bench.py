@@ -322,7 +322,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(walkers would shard across GPUs with an all-gather of R energies per exchange step)",
               file=sys.stderr)
         sys.exit(2)
