@@ -56,7 +56,9 @@ __device__ __forceinline__ int32_t load_published(const int32_t *p)
 template <typename F, int QT, bool HLDS, bool J64L>
 __device__ __forceinline__ void run_job_walker(const JobSlot &S, int w, unsigned char *lds, int32_t *done_flag, int32_t *sflag)
 {
+    // the slot may sit in host memory (serving): read it once
     Inst P = S.inst;
+    const LdsPlan plan = S.plan;
     unsigned long long *const jc = S.jc;
     const int tid = threadIdx.x, L = P.L, R = P.R;
     if (w == 0) {
@@ -105,11 +107,11 @@ __device__ __forceinline__ void run_job_walker(const JobSlot &S, int w, unsigned
         for (int j = tid; j < L; j += blockDim.x)
             P.spins[static_cast<size_t>(w) * L + j] = initial_spin(P, w, j, S.init != 0);
         __syncthreads();
-        Walker<F> W = carve<F, HLDS, J64L>(lds, S.plan, P, w);
-        load_walker<F>(P, W, S.plan, w);
+        Walker<F> W = carve<F, HLDS, J64L>(lds, plan, P, w);
+        load_walker<F>(P, W, plan, w);
         const double E = refresh_fields<F>(P, W);
         __syncthreads();
-        store_walker<F>(P, W, S.plan, w);
+        store_walker<F>(P, W, plan, w);
         if (tid == 0) {
             P.E[w] = E;
             P.Eerr[w] = 0.0;
@@ -119,7 +121,7 @@ __device__ __forceinline__ void run_job_walker(const JobSlot &S, int w, unsigned
             P.Mw[w] = (static_cast<double>(P.q) * nmax / L - 1.0) / (P.q - 1);
         }
         __syncthreads();
-        ok = run_walker<F, QT, HLDS, J64L>(P, S.plan, lds, w, 0, static_cast<int32_t>(S.sweeps), S.xevery, 0, true);
+        ok = run_walker<F, QT, HLDS, J64L>(P, plan, lds, w, 0, static_cast<int32_t>(S.sweeps), S.xevery, 0, true);
     }
     if (tid == 0) {
         if (!ok) atomicOr(&P.ctr[kCtrError], kErrBarrierTimeout);
