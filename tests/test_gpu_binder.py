@@ -36,3 +36,16 @@ def test_binder_main_prints_crossings(binder, capsys):
     out = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
     assert out["Tc_table1"] == 1.4125
     assert set(out["curves"]) == {"32", "64"}
+
+
+def test_binder_energy_cumulant_and_fit(binder, capsys):
+    binder.main(["--sigma", "0.5", "--sizes", "32,48,64", "--tmin", "1.0", "--tmax", "2.4", "--replicas", "8",
+                 "--therm", "200", "--prod", "400", "--blocks", "4", "--energy-cumulant"])
+    import json
+
+    out = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    assert out["U_E_inf_table2"] == 1.022
+    for L in ("32", "48", "64"):
+        u, du, t = out["curves"][L]["U_E_max"]
+        assert u >= 1.0 and du >= 0.0 and 1.0 <= t <= 2.4  # <E^4> >= <E^2>^2 (Jensen)
+    assert "U_E_inf" in out
