@@ -27,9 +27,15 @@ sys.path.insert(0, ROOT)
 # MI355X published peaks and unit counts
 CUS = 256
 CLOCK_HZ = 2.4e9
-LDS_BYTES_PER_CLK_CU = 128  # ds_read/ds_write bandwidth per CU per clock
-LDS_PEAK = CUS * LDS_BYTES_PER_CLK_CU * CLOCK_HZ  # 78.6 TB/s
+# LDS read bandwidth per CU per clock.  CDNA 3 reads 128 B/clk from its 64 KB
+# LDS; CDNA 4 (gfx950) grows the LDS to 160 KB and doubles its read bandwidth
+# (AMD CDNA 4 architecture whitepaper), so 256 B/clk/CU: 157.3 TB/s for the
+# chip.  The probe (conflict-free 16-byte reads) reaches about 107 TB/s, more
+# than a 128 B/clk model allows, so that model cannot be the ceiling.
+LDS_BYTES_PER_CLK_CU = 256
+LDS_PEAK = CUS * LDS_BYTES_PER_CLK_CU * CLOCK_HZ  # 157.3 TB/s
 HBM_PEAK = 8.0e12
+PLACE_NAMES = {1: "lds", 2: "hbm", 3: "direct"}
 
 
 def workload(name):
@@ -52,18 +58,58 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(obs, L, attempts, sweeps_walkers, prec):
-    """LDS bytes the method must move: per attempt s_i + two table entries;
-    per accepted flip one coupling row read and two table rows read and
-    written; per refresh one FP64 coupling read per site pair; per recheck one
-    FP64 coupling and one spin per site."""
+def algorithmic_bytes(obs, inst, prec, placement):
+    """Bytes the method must move per launch, by placement of the field table.
+
+    Table in LDS (f = 4 B FP32 / 8 B FP64 per entry): per attempt the spin s_i
+    and two table entries (1 + 2 f); per accepted flip one coupling row read
+    and two table rows read and written (5 f L); per refresh one FP64 coupling
+    per site pair (8 L^2); per recheck one FP64 coupling and one spin per site
+    (9 L).  No table (direct sums): per attempt one spin and one FP64 coupling
+    per site (9 L).  Both: per walker and sweep the energy and magnetisation
+    reductions read 5 L; per exchange step 8 R of energies."""
     fb = 4 if prec == 1 else 8
     acc = int(obs["flip_acc"].sum())
-    return (attempts * (1 + 2 * fb) + acc * 5 * fb * L + obs["n_refresh"] * 8 * L * L
-            + obs["n_recheck"] * 9 * L), acc
+    attempts = inst.L * inst.R * inst.sweeps
+    common = inst.R * inst.sweeps * 5 * inst.L + obs["exchange_steps"] * 8 * inst.R
+    if placement == 3:
+        return attempts * 9 * inst.L + common, acc
+    return (attempts * (1 + 2 * fb) + acc * 5 * fb * inst.L + obs["n_refresh"] * 8 * inst.L * inst.L
+            + obs["n_recheck"] * 9 * inst.L + common), acc
 
 
-def run_gpu(inst, prec, steps, warmup, max_chunk=0):
+def phase_summary(ph, inst, prec, placement):
+    """Phase counters of a profiled run: where each walker's cycles went, and
+    the field update measured where it runs (flush cycles inside the sweep
+    kernel) against the LDS peak of one CU."""
+    import numpy as np
+
+    fb = 4 if prec == 1 else 8
+    tot = ph["total"].astype(float)
+    share = {k: float(ph[k].sum() / tot.sum()) for k in ("draw", "chain", "flush", "record", "exchange")}
+    hot = int(np.argmax(ph["flips"]))
+    out = {"cycles_share": share,
+           "iters_per_window": float(ph["iters"].sum() / max(1, ph["windows"].sum())),
+           "flips_per_flushed_window": float(ph["flips"].sum() / max(1, ph["flushes"].sum())),
+           "hottest_walker": {"walker": hot, "flips": int(ph["flips"][hot]),
+                              "cycles_share": {k: float(ph[k][hot] / tot[hot])
+                                               for k in ("draw", "chain", "flush", "record", "exchange")},
+                              "iters_per_window": float(ph["iters"][hot] / max(1, ph["windows"][hot]))}}
+    if placement != 3 and ph["flush"].sum() > 0:
+        # algorithmic field-update bytes (5 f L per flip) per flush cycle of each
+        # walker's workgroup, i.e. per CU, against 256 B/clk/CU
+        b = ph["flips"].astype(float) * 5 * fb * inst.L
+        per_clk = b.sum() / ph["flush"].sum()
+        out["field_update_in_sweep"] = {
+            "bytes_per_clk_per_cu": per_clk, "peak_bytes_per_clk_per_cu": LDS_BYTES_PER_CLK_CU,
+            "frac": per_clk / LDS_BYTES_PER_CLK_CU,
+            "hottest_walker_frac": float(b[hot] / ph["flush"][hot] / LDS_BYTES_PER_CLK_CU),
+            "note": "flush cycles inside k_sweep (s_memtime by thread 0 between the barriers around each "
+                    "window's flush); 5 f L algorithmic bytes per accepted flip"}
+    return out
+
+
+def run_gpu(inst, prec, steps, warmup, max_chunk=0, placement=0):
     import torch
 
     import paper_1308_5426_amd as pkg
@@ -72,14 +118,18 @@ def run_gpu(inst, prec, steps, warmup, max_chunk=0):
     stream = torch.cuda.current_stream()
     t_kernel = []
     obs_last = None
+    plan = None
 
-    def one_step(timed):
-        nonlocal obs_last
+    def one_step(timed, profile=False):
+        nonlocal obs_last, plan
         sim = pkg.Simulation(inst.L, inst.q, inst.sigma, inst.T, inst.seed, precision=prec, init=inst.init,
-                             max_sweeps_per_launch=max_chunk or inst.sweeps)
+                             max_sweeps_per_launch=max_chunk or inst.sweeps, placement=placement, profile=profile)
+        plan = sim.plan()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
-        print(f"[bench] instance ready, running {inst.sweeps} sweeps", file=sys.stderr, flush=True)
+        print(f"[bench] instance ready ({PLACE_NAMES.get(plan['placement'])}, {plan['threads']} threads, "
+              f"{plan['lds_bytes']} B LDS{', profiled' if profile else ''}), running {inst.sweeps} sweeps",
+              file=sys.stderr, flush=True)
         e0.record(stream)
         done = 0
         while done < inst.sweeps:  # long runs go in launches of max_chunk sweeps, each reported
@@ -95,8 +145,10 @@ def run_gpu(inst, prec, steps, warmup, max_chunk=0):
         if timed:
             t_kernel.append(e0.elapsed_time(e1) / 1e3)
             obs_last = obs
+        ph = sim.phase_counters() if profile else None
         # the workspace returns to PyTorch's cache and is reused by the next step
         sim.close()
+        return ph
 
     for _ in range(warmup):
         one_step(False)
@@ -106,7 +158,7 @@ def run_gpu(inst, prec, steps, warmup, max_chunk=0):
         one_step(True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    return elapsed, t_kernel, obs_last
+    return elapsed, t_kernel, obs_last, plan, one_step
 
 
 def _oracle_rate(inst, seconds, mode, threads):
@@ -146,12 +198,19 @@ def cpu_baseline(inst, seconds=12.0, mode=0):
     the direct O(L) mode on all cores (the reported value), and shorter samples
     of the same mode on one core and of the FP64 field-table mode on all cores."""
     threads = min(16, os.cpu_count() or 1)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     rate, n, dt = _oracle_rate(inst, seconds, mode, threads)
     one, n1, dt1 = _oracle_rate(inst, seconds / 4, mode, 1)
     tab, n2, dt2 = _oracle_rate(inst, seconds / 4, 1 - mode, threads)
     what = "direct O(L) energy difference" if mode == 0 else "FP64 field table"
     other = "FP64 field table" if mode == 0 else "direct O(L) energy difference"
     return {"value": rate, "unit": "attempts/s", "cores": threads, "kind": "oracle",
+            "nproc": os.cpu_count(), "cpu_model": model,
             "sample": f"sweeps 2..{n + 1} of the same workload ({inst.R} replicas x {inst.L} sites, exchange "
                       f"after each sweep), oracle mode: {what}, {dt:.1f} s; also {n1} sweeps on 1 core "
                       f"({dt1:.1f} s) and {n2} sweeps of the {other} mode on {threads} threads ({dt2:.1f} s)",
@@ -316,6 +375,10 @@ def main():
                     help="first copy this many bytes device to device (a kernel of known HBM traffic, "
                          "to calibrate the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--sweeps", type=int, default=0, help="override the workload's sweep count")
+    ap.add_argument("--placement", default="auto", choices=["auto", "lds", "hbm", "direct"],
+                    help="field table placement of single instances")
+    ap.add_argument("--no-profile", action="store_true", help="skip the profiled pass (phase counters)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched workload of the default run")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
@@ -345,19 +408,21 @@ def main():
     if args.sweeps:
         inst.sweeps = args.sweeps
     prec = 1 if args.precision == "f32" else 0
+    placement = {"auto": 0, "lds": 1, "hbm": 2, "direct": 3}[args.placement]
     # the L = 16384 instance runs in launches of 250 sweeps (progress between them)
-    elapsed, tk, obs = run_gpu(inst, prec, args.steps, args.warmup, max_chunk=250 if inst.L > 8192 else 0)
+    elapsed, tk, obs, plan, one_step = run_gpu(inst, prec, args.steps, args.warmup,
+                                               max_chunk=250 if inst.L > 8192 else 0, placement=placement)
     attempts = inst.L * inst.R * inst.sweeps
     value = attempts * args.steps / elapsed
     kern = sum(tk) / len(tk)
-    bytes_, acc = algorithmic_bytes(obs, inst.L, attempts, inst.R * inst.sweeps, prec)
+    bytes_, acc = algorithmic_bytes(obs, inst, prec, plan["placement"])
     achieved = bytes_ / kern
     sha = kernel_source_sha()
     tr = load_traffic(sha, f"pmc_k_sweep_{args.workload}_{args.precision}.md")
     traffic = None if tr is None else tr["hbm_bytes_per_launch"]
     occupied = min(CUS, inst.R)
     lds_meas = lds_peak_measured()
-    peak = max(LDS_PEAK, lds_meas or 0.0)
+    peak = LDS_PEAK
     out = {
         "metric": "spin-flip attempts/sec (all replicas)",
         "value": value,
@@ -376,7 +441,8 @@ def main():
                         f"[{inst.T[0]:g},{inst.T[-1]:g}] sweeps={inst.sweeps} exchange every sweep "
                         f"{'ordered' if inst.init else 'uniform random'} spins seed={inst.seed}",
             "L": inst.L, "q": inst.q, "sigma": inst.sigma, "replicas": inst.R, "sweeps": inst.sweeps,
-            "field_table": "fp32 + fp64 recheck" if prec else "fp64",
+            "field_table": ("fp32 + fp64 recheck" if prec else "fp64") + " in " + PLACE_NAMES[plan["placement"]],
+            "threads_per_walker": plan["threads"], "lds_bytes_per_walker": plan["lds_bytes"],
         },
         "roofline": {
             "bound": "lds",
@@ -386,9 +452,12 @@ def main():
             "unit": "GB/s",
             "frac": achieved / peak,
             "frac_occupied_cus": achieved / (peak * occupied / CUS),
-            "peak_nominal": LDS_PEAK / 1e9,
-            "peak_measured": None if lds_meas is None else lds_meas / 1e9,
+            "peak_note": "256 B/clk/CU x 256 CUs x 2.4 GHz (CDNA 4 LDS read bandwidth); the probe's measured "
+                         "rate is an achievable reference, not the peak",
+            "probe_measured": None if lds_meas is None else lds_meas / 1e9,
             "traffic": traffic,
+            "traffic_note": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated by a copy kernel) from "
+                            "the committed counter summary of these kernel sources, else null",
             "kernel_ms": kern * 1e3,
             "algorithmic_bytes_per_launch": bytes_,
             "accepted_flips_per_launch": acc,
@@ -399,10 +468,23 @@ def main():
             "source_sha": sha,
         },
     }
+    if not args.no_profile:
+        # one more (untimed) pass of the same step with the phase counters on
+        print("[bench] profiled pass", file=sys.stderr, flush=True)
+        ph = one_step(False, profile=True)
+        out["phases"] = phase_summary(ph, inst, prec, plan["placement"])
     if not prec and inst.q <= 4 and inst.L <= 3000:
         out["field_update_alone"] = field_update_alone(inst, peak)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds, mode=0)
+    if args.workload == "medium" and not args.no_batch:
+        print("[bench] batched workload: 256 jobs x 1000 sweeps in one launch", file=sys.stderr, flush=True)
+        b = run_batch(argparse.Namespace(jobs=256, sweeps=1000, precision=args.precision, autotune=False,
+                                         threads=0, lds=0, steps=1, warmup=0, plain_sample=args.plain_sample))
+        out["batched"] = {"metric": b["metric"], "value": b["value"], "unit": b["unit"],
+                          "seconds": b["ms_per_step"] / 1e3, "config": b["config"],
+                          "plain_per_instance": b["plain_per_instance"],
+                          "batched_over_plain": b["value"] / b["plain_per_instance"]["value"]}
     print(json.dumps(out), flush=True)
 
 

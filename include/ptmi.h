@@ -55,7 +55,10 @@ typedef enum {
 
 enum { PT_PREC_F64 = 0, PT_PREC_F32 = 1 };
 enum { PT_INIT_RANDOM = 0, PT_INIT_ORDERED = 1 };
-enum { PT_PLACE_AUTO = 0, PT_PLACE_LDS = 1, PT_PLACE_HBM = 2 };
+/* Placement of a walker's field table during its sweeps: in LDS, in HBM
+ * (couplings and spins in LDS), or no table at all (every energy change a
+ * direct FP64 sum over the spins, the paper's own per-attempt scheme). */
+enum { PT_PLACE_AUTO = 0, PT_PLACE_LDS = 1, PT_PLACE_HBM = 2, PT_PLACE_DIRECT = 3 };
 
 /* Kernel limit on the number of Potts states. */
 #define PT_QMAX 16
@@ -67,7 +70,8 @@ typedef struct {
     int32_t precision;      /* PT_PREC_F64: FP64 field table; PT_PREC_F32: FP32 table
                                with FP64 recheck of near-threshold attempts */
     int32_t init;           /* PT_INIT_RANDOM or PT_INIT_ORDERED (all spins 1) */
-    int32_t placement;      /* where the field table lives during a sweep */
+    int32_t placement;      /* PT_PLACE_*: where the field table lives during a sweep (AUTO:
+                               LDS when it fits, else no table, direct sums) */
     int32_t threads;        /* threads per walker workgroup (multiple of 64, <= 256); 0 = auto
                                (single instance: 64 per 256 sites, at most 256; batch/server: 256) */
     int32_t refresh_every;  /* sweeps between O(L^2) recomputations of the fields; 0 = auto */
@@ -75,6 +79,7 @@ typedef struct {
     int32_t event_capacity; /* entries of the banded-event log (0 = 4096) */
     int32_t max_sweeps_per_launch; /* 0 = auto */
     int32_t lds_budget;     /* batch/server: LDS bytes per walker workgroup (0 = all the device allows) */
+    int32_t profile;        /* 1: keep per-walker phase counters (pt_get_phase_counters) */
     void *stream;           /* hipStream_t to run on, NULL = the null stream */
     void *workspace;        /* optional caller-owned device memory for all state */
     size_t workspace_bytes; /* its size; must be >= pt_workspace_size() */
@@ -133,10 +138,11 @@ pt_status pt_sweep(pt_ctx *ctx, int64_t n);
 /* One exchange step (eq. 9): even stage then odd stage.  Asynchronous. */
 pt_status pt_exchange(pt_ctx *ctx);
 
-/* n sweeps with an exchange step after every exchange_every-th sweep, in
- * persistent cooperative launches with a device-side grid barrier (no host
- * round trip per sweep).  exchange_every = 0 behaves like pt_sweep.
- * Asynchronous. */
+/* n sweeps with an exchange step after sweeps exchange_every, 2 exchange_every,
+ * ... counted from the start of this call, in persistent cooperative launches
+ * with a device-side grid barrier (no host round trip per sweep); the
+ * schedule does not depend on how the sweeps are split into launches.
+ * exchange_every = 0 behaves like pt_sweep.  Asynchronous. */
 pt_status pt_run(pt_ctx *ctx, int64_t n, int32_t exchange_every);
 
 /* Waits for queued work and copies observables to the host.  Synchronising. */
@@ -156,6 +162,31 @@ pt_status pt_get_series(pt_ctx *ctx, double *E, double *M, int64_t cap_rows, int
 /* Logged near-threshold events (up to cap); *n_out receives the count stored. */
 pt_status pt_get_events(pt_ctx *ctx, pt_event *out, int64_t cap, int64_t *n_out);
 
+/* The launch plan chosen at pt_init: placement (PT_PLACE_LDS, _HBM or
+ * _DIRECT), threads per walker workgroup and LDS bytes per workgroup of the
+ * persistent sweep launch.  Any pointer may be NULL.  Host only. */
+pt_status pt_get_plan(pt_ctx *ctx, int32_t *placement, int32_t *threads, int32_t *lds_bytes);
+
+/* Phase counters of each walker, kept when pt_options.profile was set at
+ * pt_init: shader-clock cycles (s_memtime) its workgroup spent in each phase,
+ * summed over every launch since pt_init, and event counts.  out is caller
+ * host memory of R * PT_PHASE_N uint64, by walker.  Synchronising.
+ * PT_ESTATE if profiling is off. */
+enum {
+    PT_PHASE_DRAW = 0,      /* Philox draws of the attempts, staged in LDS            */
+    PT_PHASE_CHAIN = 1,     /* Metropolis decisions (eq. 8) through the windows        */
+    PT_PHASE_FLUSH = 2,     /* accepted flips applied to the field table               */
+    PT_PHASE_RECORD = 3,    /* end-of-sweep energy sums, observables, refreshes        */
+    PT_PHASE_EXCHANGE = 4,  /* device barrier and exchange step (eq. 9)                */
+    PT_PHASE_TOTAL = 5,     /* the walker's whole loop                                 */
+    PT_PHASE_WINDOWS = 6,   /* count: windows of 64 attempts                           */
+    PT_PHASE_FLUSHES = 7,   /* count: windows with flips to apply                      */
+    PT_PHASE_FLIPS = 8,     /* count: accepted flips                                   */
+    PT_PHASE_ITERS = 9,     /* count: guess-and-check iterations of the chain          */
+    PT_PHASE_N = 10
+};
+pt_status pt_get_phase_counters(pt_ctx *ctx, uint64_t *out);
+
 /* Zeroes the moment and acceptance accumulators (e.g. after burn-in). */
 pt_status pt_reset_stats(pt_ctx *ctx);
 
@@ -165,7 +196,9 @@ pt_status pt_synchronize(pt_ctx *ctx);
 
 /* Checkpoint: the complete state is (spins, perm, sweep and exchange
  * counters, accumulators, seed, parameters); fields are rebuilt on load.
- * pt_save with buf == NULL returns the needed size in *len. */
+ * pt_save with buf == NULL returns the needed size in *len.  pt_load checks a
+ * buffer on the host before any device call (sizes, every spin below q, perm
+ * a permutation) and returns PT_EINVAL for a corrupt one. */
 pt_status pt_save(pt_ctx *ctx, void *buf, size_t *len);
 pt_status pt_load(pt_ctx **out, const void *buf, size_t len, const pt_options *opt);
 

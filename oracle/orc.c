@@ -217,10 +217,13 @@ orc_pt *orc_pt_create_at(int32_t L, int32_t q, double sigma, const double *T, in
             p->s[(size_t)w * L + j] = v;
         }
     p->E = (double *)malloc(sizeof(double) * R);
-    for (int32_t w = 0; w < R; ++w) p->E[w] = orc_energy(L, p->J, p->s + (size_t)w * L);
-    if (mode == 1) {
-        p->h = (double *)malloc(sizeof(double) * (size_t)R * q * L);
-        for (int32_t w = 0; w < R; ++w) fields_from_spins(p, w);
+    if (mode == 1) p->h = (double *)malloc(sizeof(double) * (size_t)R * q * L);
+    /* walkers are independent: their O(L^2) initial energies (and fields) are
+       computed in parallel, each by the same sequential loop */
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t w = 0; w < R; ++w) {
+        p->E[w] = orc_energy(L, p->J, p->s + (size_t)w * L);
+        if (mode == 1) fields_from_spins(p, w);
     }
     p->perm = (int32_t *)malloc(sizeof(int32_t) * R);
     p->slot = (int32_t *)malloc(sizeof(int32_t) * R);

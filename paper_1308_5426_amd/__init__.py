@@ -23,7 +23,8 @@ LIB_PATH = os.path.join(_HERE, "libptmi.so")
 PT_OK, PT_EINVAL, PT_ENOMEM, PT_EDEVICE, PT_ESTATE = 0, -1, -2, -3, -4
 PREC_F64, PREC_F32 = 0, 1
 INIT_RANDOM, INIT_ORDERED = 0, 1
-PLACE_AUTO, PLACE_LDS, PLACE_HBM = 0, 1, 2
+PLACE_AUTO, PLACE_LDS, PLACE_HBM, PLACE_DIRECT = 0, 1, 2, 3
+PHASES = ("draw", "chain", "flush", "record", "exchange", "total", "windows", "flushes", "flips", "iters")
 QMAX = 16
 BAND = 1e-9
 
@@ -45,6 +46,7 @@ class Options(ctypes.Structure):
         ("event_capacity", ctypes.c_int32),
         ("max_sweeps_per_launch", ctypes.c_int32),
         ("lds_budget", ctypes.c_int32),
+        ("profile", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
@@ -80,7 +82,7 @@ class JobDesc(ctypes.Structure):
 EXPORTS = [
     "pt_default_options", "pt_workspace_size", "pt_init", "pt_sweep", "pt_exchange", "pt_run",
     "pt_observables", "pt_get_spins", "pt_get_jstar", "pt_get_series", "pt_get_events",
-    "pt_reset_stats", "pt_synchronize", "pt_save", "pt_load", "pt_free", "pt_last_error",
+    "pt_get_plan", "pt_get_phase_counters", "pt_reset_stats", "pt_synchronize", "pt_save", "pt_load", "pt_free", "pt_last_error",
     "pt_batch_workspace_size", "pt_batch_create", "pt_batch_run", "pt_batch_observables",
     "pt_batch_get_spins", "pt_batch_shape", "pt_batch_free",
     "pt_server_start", "pt_server_submit", "pt_server_poll", "pt_server_wait", "pt_server_times",
@@ -117,6 +119,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.pt_get_jstar.argtypes = [_P, _P]
     L.pt_get_series.argtypes = [_P, _P, _P, i64, ctypes.POINTER(i64)]
     L.pt_get_events.argtypes = [_P, _P, i64, ctypes.POINTER(i64)]
+    L.pt_get_phase_counters.argtypes = [_P, _P]
+    L.pt_get_plan.argtypes = [_P, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.pt_reset_stats.argtypes = [_P]
     L.pt_synchronize.argtypes = [_P]
     L.pt_save.argtypes = [_P, _P, ctypes.POINTER(ctypes.c_size_t)]
@@ -206,7 +210,7 @@ class Simulation:
 
     def __init__(self, L, q, sigma, T, seed, precision=PREC_F64, init=INIT_RANDOM, threads=0,
                  refresh_every=0, series_capacity=0, event_capacity=0, max_sweeps_per_launch=0,
-                 placement=PLACE_AUTO, _ctx=None, _ws=None):
+                 placement=PLACE_AUTO, profile=False, _ctx=None, _ws=None):
         self._lib = load_library()
         self.L, self.q, self.sigma, self.seed = int(L), int(q), float(sigma), int(seed)
         self.T = np.ascontiguousarray(np.asarray(T, dtype=np.float64))
@@ -217,6 +221,7 @@ class Simulation:
             return
         opt = self._options(precision, init, threads, refresh_every, series_capacity, event_capacity,
                             max_sweeps_per_launch, placement)
+        opt.profile = 1 if profile else 0
         nbytes = ctypes.c_size_t(0)
         _check(self._lib.pt_workspace_size(self.L, self.q, self.R, ctypes.byref(opt), ctypes.byref(nbytes)))
         self._ws, stream = _torch_device_memory(nbytes.value)
@@ -275,22 +280,22 @@ class Simulation:
 
     # -- results -------------------------------------------------------------
     def observables(self) -> dict:
-        R = self.R
-        arrs = {k: np.zeros(R) for k in ("E", "M", "sumE", "sumE2", "sumE4", "sumM", "sumM2", "sumM4")}
-        ints = {k: np.zeros(R, np.int64) for k in ("flip_att", "flip_acc")}
-        pairs = {k: np.zeros(max(R - 1, 1), np.int64) for k in ("xchg_att", "xchg_acc")}
-        perm = np.zeros(R, np.int32)
-        o = Obs()
-        for k, v in {**arrs, **ints, **pairs}.items():
-            setattr(o, k, _ptr(v))
-        o.perm = _ptr(perm)
+        o, arrs, ints, pairs, perm = _obs_buffers(self.R)
         _check(self._lib.pt_observables(self._ctx, ctypes.byref(o)))
-        out = {**arrs, **ints}
-        out.update({k: v[: R - 1] for k, v in pairs.items()})
-        out.update(perm=perm, sweeps=o.sweeps, exchange_steps=o.exchange_steps, samples=o.samples,
-                   n_recheck=o.n_recheck, n_banded=o.n_banded, n_exact_energy=o.n_exact_energy,
-                   n_refresh=o.n_refresh, n_events_dropped=o.n_events_dropped)
-        return out
+        return _obs_dict(o, arrs, ints, pairs, perm, self.R)
+
+    def plan(self) -> dict:
+        """Launch plan chosen at init: placement (PLACE_LDS/HBM/DIRECT), threads, LDS bytes."""
+        p, t, l = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(self._lib.pt_get_plan(self._ctx, ctypes.byref(p), ctypes.byref(t), ctypes.byref(l)))
+        return dict(placement=p.value, threads=t.value, lds_bytes=l.value)
+
+    def phase_counters(self) -> dict:
+        """Per-walker phase counters (needs profile=True): cycles per phase and
+        counts, each an array [R] by walker, keyed by the names in PHASES."""
+        out = np.zeros((self.R, len(PHASES)), np.uint64)
+        _check(self._lib.pt_get_phase_counters(self._ctx, _ptr(out)))
+        return {name: out[:, k].astype(np.int64) for k, name in enumerate(PHASES)}
 
     def spins(self):
         """(spins [R][L] by walker, values 1..q; perm [R] slot -> walker)."""

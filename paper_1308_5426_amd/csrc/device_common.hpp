@@ -119,6 +119,21 @@ __device__ __forceinline__ void jstar_entry(int32_t L, double sigma, int r, doub
     }
 }
 
+// Zero fill of device memory (used instead of a memset node, so the call can
+// also be captured in a graph): 8-byte words when pointer and size allow,
+// bytes otherwise.
+__global__ void k_zero(unsigned char *__restrict__ p, size_t n)
+{
+    const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+    const size_t t0 = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if ((reinterpret_cast<uintptr_t>(p) & 7u) == 0 && (n & 7u) == 0) {
+        uint64_t *w = reinterpret_cast<uint64_t *>(p);
+        for (size_t e = t0; e < n / 8; e += stride) w[e] = 0ull;
+    } else {
+        for (size_t e = t0; e < n; e += stride) p[e] = 0;
+    }
+}
+
 __global__ void k_jstar(int32_t L, double sigma, double *__restrict__ J64, float *__restrict__ J32)
 {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;

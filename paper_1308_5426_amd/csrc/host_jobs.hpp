@@ -264,8 +264,9 @@ pt_status pt_batch_run(pt_batch *b)
 {
     if (!b) return fail(PT_EINVAL, "null batch");
     if (b->ran) return fail(PT_ESTATE, "batch already ran");
-    HIPCHK(hipMemsetAsync(b->ws, 0, b->slots_off, b->stream));
-    HIPCHK(hipMemsetAsync(b->d_ctl, 0, b->T_off - b->ctl_off, b->stream));  // ticket and ready/finished words
+    pt_status st = zero_async(b->ws, b->slots_off, b->stream);
+    if (st == PT_OK) st = zero_async(b->d_ctl, b->T_off - b->ctl_off, b->stream);  // ticket and ready/finished words
+    if (st != PT_OK) return st;
     HIPCHK(hipMemcpyAsync(b->d_slots, b->slots.data(), sizeof(JobSlot) * b->njobs, hipMemcpyHostToDevice, b->stream));
     HIPCHK(hipMemcpyAsync(b->d_T, b->Tall.data(), sizeof(double) * b->Tall.size(), hipMemcpyHostToDevice, b->stream));
     const JobSlot *slots = b->d_slots;
@@ -534,8 +535,7 @@ pt_status pt_server_start(pt_server **out, size_t arena_bytes, int32_t max_jobs,
     s->grid = cap;
     s->free_blocks[0] = s->arena_bytes;
     // ticket and every slot's ready/finished words start at zero with the launch
-    if (hipMemsetAsync(s->d_ctl, 0, total - s->ctl_off, s->kstream) != hipSuccess)
-        return bail(fail(PT_EDEVICE, "memset failed"));
+    if (zero_async(s->d_ctl, total - s->ctl_off, s->kstream) != PT_OK) return bail(PT_EDEVICE);
     const JobSlot *slots = s->h_slots;
     int32_t nstatic = -1;
     const int32_t *pub = s->h_ctl, *stop = s->h_ctl + 1;

@@ -121,7 +121,7 @@ __device__ __forceinline__ void run_job_walker(const JobSlot &S, int w, unsigned
             P.Mw[w] = (static_cast<double>(P.q) * nmax / L - 1.0) / (P.q - 1);
         }
         __syncthreads();
-        ok = run_walker<F, QT, HLDS, J64L>(P, plan, lds, w, 0, static_cast<int32_t>(S.sweeps), S.xevery, 0, true);
+        ok = run_walker<F, QT, HLDS, J64L>(P, plan, lds, w, 0, static_cast<int32_t>(S.sweeps), S.xevery, 0, 0, true);
     }
     if (tid == 0) {
         if (!ok) atomicOr(&P.ctr[kCtrError], kErrBarrierTimeout);

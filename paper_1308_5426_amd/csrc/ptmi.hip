@@ -61,6 +61,7 @@ struct pt_ctx {
     LdsPlan plan{}, plan_fused{};
     bool can_fuse = false;
     bool h_in_lds = true;
+    bool prof = false;
     int64_t sweeps = 0, xsteps = 0, samples = 0;
     std::vector<double> T;
 };
@@ -148,9 +149,9 @@ bool make_plan(int L, int q, int R, int prec, bool fused, bool h_in_lds, size_t 
     return false;
 }
 
-Layout layout_of(int L, int q, int R, int prec, int ser_cap, int ev_cap)
+Layout layout_of(int L, int q, int R, int prec, int ser_cap, int ev_cap, bool prof = false)
 {
-    return Layout(L, q, R, field_bytes(prec), ser_cap, ev_cap);
+    return Layout(L, q, R, field_bytes(prec), ser_cap, ev_cap, prof);
 }
 
 pt_status validate(int32_t L, int32_t q, double sigma, const double *T, int32_t R)
@@ -214,12 +215,12 @@ pt_status launch_refresh(pt_ctx *c)
 }
 
 template <typename F>
-pt_status launch_sweep(pt_ctx *c, int64_t n0, int32_t nsw, int32_t xevery, int64_t m0, bool fused)
+pt_status launch_sweep(pt_ctx *c, int64_t n0, int32_t nsw, int32_t xevery, int32_t x0, int64_t m0, bool fused)
 {
     Inst P = c->inst;
     LdsPlan plan = fused ? c->plan_fused : c->plan;
     int32_t fu = fused ? 1 : 0;
-    void *args[] = {&P, &plan, &n0, &nsw, &xevery, &m0, &fu};
+    void *args[] = {&P, &plan, &n0, &nsw, &xevery, &x0, &m0, &fu};
     if (fused)
         HIPCHK(hipLaunchCooperativeKernel(sweep_fn<F>(c->q, plan), dim3(c->R), dim3(c->NT), args, plan.total, c->stream));
     else
@@ -232,6 +233,17 @@ pt_status launch_exchange(pt_ctx *c)
     const int bytes = 256 + 40 * c->R;
     hipLaunchKernelGGL(k_exchange, dim3(1), dim3(std::min(1024, std::max(64, ((c->R + 63) / 64) * 64))),
                        bytes, c->stream, c->inst, c->xsteps);
+    HIPCHK(hipGetLastError());
+    return PT_OK;
+}
+
+// Queues a zero fill of n bytes at p on stream st.
+pt_status zero_async(void *p, size_t n, hipStream_t st)
+{
+    if (n == 0) return PT_OK;
+    const size_t words = (n + 7) / 8;
+    const unsigned blocks = static_cast<unsigned>(std::min<size_t>(2048, (words + 255) / 256));
+    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, st, static_cast<unsigned char *>(p), n);
     HIPCHK(hipGetLastError());
     return PT_OK;
 }
@@ -256,7 +268,7 @@ pt_status device_error(pt_ctx *c)
 
 // Points an instance's arrays into its workspace block.
 void fill_inst(Inst &P, unsigned char *b, const Layout &lay, int L, int q, int R, uint64_t seed, int refresh_every,
-               int ser_cap, int ev_cap)
+               int ser_cap, int ev_cap, bool prof = false)
 {
     P = Inst{};
     P.L = L; P.q = q; P.R = R; P.walker0 = 0;
@@ -287,6 +299,7 @@ void fill_inst(Inst &P, unsigned char *b, const Layout &lay, int L, int q, int R
     P.ev_cap = ev_cap;
     P.ctr = reinterpret_cast<unsigned long long *>(b + lay.ctr);
     P.bnd = reinterpret_cast<TableBounds *>(b + lay.bnd);
+    P.phase = prof ? reinterpret_cast<unsigned long long *>(b + lay.phase) : nullptr;
 }
 
 // Host copy of an instance's observables (by walker / slot as on the device).
@@ -386,7 +399,7 @@ pt_status pt_workspace_size(int32_t L, int32_t q, int32_t R, const pt_options *o
     pt_default_options(&d);
     const pt_options &o = opt ? *opt : d;
     const int ev = o.event_capacity > 0 ? o.event_capacity : 4096;
-    *bytes = layout_of(L, q, R, o.precision, std::max(0, o.series_capacity), ev).total;
+    *bytes = layout_of(L, q, R, o.precision, std::max(0, o.series_capacity), ev, o.profile != 0).total;
     return PT_OK;
 }
 
@@ -400,7 +413,8 @@ static pt_status init_impl(pt_ctx **out, int32_t L, int32_t q, double sigma, con
     if (o.init != PT_INIT_RANDOM && o.init != PT_INIT_ORDERED) return fail(PT_EINVAL, "bad init");
     if (o.threads && (o.threads % kWave || o.threads < kWave || o.threads > kMaxSweepThreads))
         return fail(PT_EINVAL, "threads must be a multiple of 64 in [64, %d]", kMaxSweepThreads);
-    if (o.placement < PT_PLACE_AUTO || o.placement > PT_PLACE_HBM) return fail(PT_EINVAL, "bad placement");
+    if (o.placement < PT_PLACE_AUTO || o.placement > PT_PLACE_DIRECT) return fail(PT_EINVAL, "bad placement");
+    if (o.placement == PT_PLACE_HBM) return fail(PT_EINVAL, "placement PT_PLACE_HBM is not available in this build");
 
     pt_ctx *c = new (std::nothrow) pt_ctx();
     if (!c) return fail(PT_ENOMEM, "host allocation failed");
@@ -408,6 +422,7 @@ static pt_status init_impl(pt_ctx **out, int32_t L, int32_t q, double sigma, con
     c->NT = o.threads ? o.threads : auto_threads(L);
     c->ser_cap = std::max(0, o.series_capacity);
     c->ev_cap = o.event_capacity > 0 ? o.event_capacity : 4096;
+    c->prof = o.profile != 0;
     c->stream = static_cast<hipStream_t>(o.stream);
     c->T.assign(T, T + R);
     auto bail = [&](pt_status st) {
@@ -423,7 +438,7 @@ static pt_status init_impl(pt_ctx **out, int32_t L, int32_t q, double sigma, con
         return bail(fail(PT_EDEVICE, "device query failed"));
     // Field table in LDS when it fits (or when asked), else its rows stay in HBM.
     const size_t lmax = static_cast<size_t>(lds_max);
-    bool in_lds = o.placement != PT_PLACE_HBM && make_plan(L, q, R, c->prec, false, true, lmax, c->NT, &c->plan);
+    bool in_lds = o.placement != PT_PLACE_DIRECT && make_plan(L, q, R, c->prec, false, true, lmax, c->NT, &c->plan);
     if (o.placement == PT_PLACE_LDS && !in_lds)
         return bail(fail(PT_EINVAL, "field table of %d x %d entries does not fit in %d B of LDS", q, L, lds_max));
     if (!in_lds && !make_plan(L, q, R, c->prec, false, false, lmax, c->NT, &c->plan))
@@ -439,7 +454,7 @@ static pt_status init_impl(pt_ctx **out, int32_t L, int32_t q, double sigma, con
     }
     c->h_in_lds = in_lds;
 
-    const Layout lay = layout_of(L, q, R, c->prec, c->ser_cap, c->ev_cap);
+    const Layout lay = layout_of(L, q, R, c->prec, c->ser_cap, c->ev_cap, c->prof);
     if (o.workspace) {
         if (o.workspace_bytes < lay.total)
             return bail(fail(PT_ENOMEM, "workspace of %zu B < %zu B needed", o.workspace_bytes, lay.total));
@@ -452,12 +467,12 @@ static pt_status init_impl(pt_ctx **out, int32_t L, int32_t q, double sigma, con
     }
     Inst &P = c->inst;
     fill_inst(P, c->ws, lay, L, q, R, seed, o.refresh_every > 0 ? o.refresh_every : (c->prec == PT_PREC_F32 ? 32 : 0),
-              c->ser_cap, c->ev_cap);
+              c->ser_cap, c->ev_cap, c->prof);
     c->refresh_every = P.refresh_every;
 
-    // hipMemset on the (possibly caller-provided) workspace: zero counters,
-    // accumulators and the barrier words.
-    if (hipMemsetAsync(c->ws, 0, lay.total, c->stream) != hipSuccess) return bail(fail(PT_EDEVICE, "memset failed"));
+    // zero the (possibly caller-provided) workspace: counters, accumulators
+    // and the barrier words start at zero
+    if (zero_async(c->ws, lay.total, c->stream) != PT_OK) return bail(PT_EDEVICE);
     std::vector<double> beta(R);
     std::vector<int32_t> ident(R);
     for (int k = 0; k < R; ++k) {
@@ -521,8 +536,8 @@ pt_status pt_sweep(pt_ctx *c, int64_t n)
     if (n < 0) return fail(PT_EINVAL, "n < 0");
     while (n > 0) {
         const int32_t chunk = static_cast<int32_t>(std::min<int64_t>(n, c->max_chunk));
-        st = c->prec == PT_PREC_F32 ? launch_sweep<float>(c, c->sweeps, chunk, 0, c->xsteps, false)
-                                    : launch_sweep<double>(c, c->sweeps, chunk, 0, c->xsteps, false);
+        st = c->prec == PT_PREC_F32 ? launch_sweep<float>(c, c->sweeps, chunk, 0, 0, c->xsteps, false)
+                                    : launch_sweep<double>(c, c->sweeps, chunk, 0, 0, c->xsteps, false);
         if (st != PT_OK) return st;
         c->sweeps += chunk;
         c->samples += chunk;
@@ -547,25 +562,28 @@ pt_status pt_run(pt_ctx *c, int64_t n, int32_t every)
     if (st != PT_OK) return st;
     if (n < 0 || every < 0) return fail(PT_EINVAL, "n and exchange_every must be >= 0");
     if (every == 0) return pt_sweep(c, n);
+    // The schedule counts sweeps from the start of this call: an exchange step
+    // follows sweeps every, 2 every, ... of the call, however the sweeps are
+    // split into launches.
     if (!c->can_fuse) {
         for (int64_t s = 0; s < n; ++s) {
             if ((st = pt_sweep(c, 1)) != PT_OK) return st;
-            if ((c->sweeps % every) == 0 && (st = pt_exchange(c)) != PT_OK) return st;
+            if ((s + 1) % every == 0 && (st = pt_exchange(c)) != PT_OK) return st;
         }
         return PT_OK;
     }
-    while (n > 0) {
-        // chunks hold whole exchange periods so the schedule is the same as unfused
-        int64_t chunk = std::min<int64_t>(n, c->max_chunk);
-        if (chunk >= every) chunk -= chunk % every;
-        const int64_t nx = chunk / every;
-        st = c->prec == PT_PREC_F32 ? launch_sweep<float>(c, c->sweeps, static_cast<int32_t>(chunk), every, c->xsteps, true)
-                                    : launch_sweep<double>(c, c->sweeps, static_cast<int32_t>(chunk), every, c->xsteps, true);
+    for (int64_t done = 0; done < n;) {
+        const int64_t chunk = std::min<int64_t>(n - done, c->max_chunk);
+        const int32_t x0 = static_cast<int32_t>(done % every);  // sweeps of the current period already run
+        const int64_t nx = (x0 + chunk) / every;                 // exchange steps inside this launch
+        st = c->prec == PT_PREC_F32
+                 ? launch_sweep<float>(c, c->sweeps, static_cast<int32_t>(chunk), every, x0, c->xsteps, true)
+                 : launch_sweep<double>(c, c->sweeps, static_cast<int32_t>(chunk), every, x0, c->xsteps, true);
         if (st != PT_OK) return st;
         c->sweeps += chunk;
         c->samples += chunk;
         c->xsteps += nx;
-        n -= chunk;
+        done += chunk;
     }
     return PT_OK;
 }
@@ -639,16 +657,38 @@ pt_status pt_get_events(pt_ctx *c, pt_event *out, int64_t cap, int64_t *n_out)
     return PT_OK;
 }
 
+pt_status pt_get_plan(pt_ctx *c, int32_t *placement, int32_t *threads, int32_t *lds_bytes)
+{
+    pt_status st = check_ctx(c);
+    if (st != PT_OK) return st;
+    const LdsPlan &p = c->can_fuse ? c->plan_fused : c->plan;
+    if (placement) *placement = p.h_in_lds ? PT_PLACE_LDS : PT_PLACE_DIRECT;
+    if (threads) *threads = c->NT;
+    if (lds_bytes) *lds_bytes = p.total;
+    return PT_OK;
+}
+
+pt_status pt_get_phase_counters(pt_ctx *c, uint64_t *out)
+{
+    pt_status st = check_ctx(c);
+    if (st != PT_OK) return st;
+    if (!out) return fail(PT_EINVAL, "out is NULL");
+    if (!c->prof) return fail(PT_ESTATE, "profiling was not enabled at pt_init (pt_options.profile)");
+    if ((st = pt_synchronize(c)) != PT_OK) return st;
+    HIPCHK(hipMemcpy(out, c->inst.phase, sizeof(uint64_t) * kPhN * c->R, hipMemcpyDeviceToHost));
+    return PT_OK;
+}
+
 pt_status pt_reset_stats(pt_ctx *c)
 {
     pt_status st = check_ctx(c);
     if (st != PT_OK) return st;
     const Inst &P = c->inst;
-    HIPCHK(hipMemsetAsync(P.acc6, 0, sizeof(double) * 6 * c->R, c->stream));
-    HIPCHK(hipMemsetAsync(P.fatt, 0, sizeof(int64_t) * c->R, c->stream));
-    HIPCHK(hipMemsetAsync(P.facc, 0, sizeof(int64_t) * c->R, c->stream));
-    HIPCHK(hipMemsetAsync(P.xatt, 0, sizeof(int64_t) * c->R, c->stream));
-    HIPCHK(hipMemsetAsync(P.xacc, 0, sizeof(int64_t) * c->R, c->stream));
+    void *arrs[5] = {P.acc6, P.fatt, P.facc, P.xatt, P.xacc};
+    const size_t bytes[5] = {sizeof(double) * 6 * c->R, sizeof(int64_t) * c->R, sizeof(int64_t) * c->R,
+                             sizeof(int64_t) * c->R, sizeof(int64_t) * c->R};
+    for (int a = 0; a < 5; ++a)
+        if ((st = zero_async(arrs[a], bytes[a], c->stream)) != PT_OK) return st;
     c->samples = 0;
     return PT_OK;
 }
@@ -702,6 +742,8 @@ pt_status pt_load(pt_ctx **out, const void *buf, size_t len, const pt_options *o
     if (len < sizeof hd) return fail(PT_EINVAL, "buffer too short");
     std::memcpy(&hd, buf, sizeof hd);
     if (hd.magic != kMagic || hd.version != kVersion) return fail(PT_EINVAL, "not a checkpoint of this library");
+    if (hd.L < 2 || hd.L > 65535 || hd.q < 2 || hd.q > PT_QMAX || hd.R < 1 || hd.R > (1 << 24))
+        return fail(PT_EINVAL, "corrupt checkpoint: sizes");
     const int R = hd.R, L = hd.L;
     const size_t need = sizeof hd + sizeof(double) * R + static_cast<size_t>(R) * L + sizeof(int32_t) * R +
                         sizeof(double) * 6 * R + sizeof(int64_t) * 4 * R;
@@ -711,6 +753,24 @@ pt_status pt_load(pt_ctx **out, const void *buf, size_t len, const pt_options *o
     std::memcpy(T.data(), p, sizeof(double) * R); p += sizeof(double) * R;
     pt_status st = validate(L, hd.q, hd.sigma, T.data(), R);
     if (st != PT_OK) return st;
+    if (hd.prec != PT_PREC_F64 && hd.prec != PT_PREC_F32) return fail(PT_EINVAL, "corrupt checkpoint: precision");
+    if (hd.init != PT_INIT_RANDOM && hd.init != PT_INIT_ORDERED) return fail(PT_EINVAL, "corrupt checkpoint: init");
+    if (hd.sweeps < 0 || hd.xsteps < 0 || hd.samples < 0) return fail(PT_EINVAL, "corrupt checkpoint: counters");
+    // every spin a state 0..q-1 and perm a permutation of 0..R-1, checked on
+    // the host before anything reaches the device (kernels index by them)
+    {
+        const unsigned char *sp = p;
+        for (size_t e = 0; e < static_cast<size_t>(R) * L; ++e)
+            if (sp[e] >= hd.q)
+                return fail(PT_EINVAL, "corrupt checkpoint: spin %zu is %d, not below q = %d", e, sp[e], hd.q);
+        int32_t pk = 0;
+        std::vector<unsigned char> seen(R, 0);
+        for (int k = 0; k < R; ++k) {
+            std::memcpy(&pk, sp + static_cast<size_t>(R) * L + sizeof(int32_t) * k, sizeof pk);
+            if (pk < 0 || pk >= R || seen[pk]) return fail(PT_EINVAL, "corrupt checkpoint: perm is not a permutation");
+            seen[pk] = 1;
+        }
+    }
     pt_options o;
     if (opt) o = *opt; else pt_default_options(&o);
     o.precision = hd.prec;
@@ -725,10 +785,7 @@ pt_status pt_load(pt_ctx **out, const void *buf, size_t len, const pt_options *o
         return fail_free(fail(PT_EDEVICE, "copy failed"));
     p += static_cast<size_t>(R) * L;
     std::memcpy(perm.data(), p, sizeof(int32_t) * R); p += sizeof(int32_t) * R;
-    for (int k = 0; k < R; ++k) {
-        if (perm[k] < 0 || perm[k] >= R) return fail_free(fail(PT_EINVAL, "corrupt permutation"));
-        slot[perm[k]] = k;
-    }
+    for (int k = 0; k < R; ++k) slot[perm[k]] = k;  // a permutation (checked above)
     if (hipMemcpy(P.perm, perm.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(P.slot_of, slot.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(P.acc6, p, sizeof(double) * 6 * R, hipMemcpyHostToDevice) != hipSuccess)

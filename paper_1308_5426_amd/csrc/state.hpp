@@ -22,6 +22,24 @@ enum Counter : int {
 };
 enum : unsigned long long { kErrBarrierTimeout = 1ull, kErrBadLaunch = 2ull };
 
+// Per-walker phase counters (uint64, Inst::phase[w * kPhN + k]), kept when
+// profiling is on: shader-clock cycles spent by the walker's workgroup in each
+// phase of its sweeps (read by thread 0 right after the barrier that closes
+// the phase), and event counts.
+enum Phase : int {
+    kPhDraw = 0,        // generating the chunk's draws
+    kPhChain = 1,       // the Metropolis chain through the windows
+    kPhFlush = 2,       // applying the windows' flips to the field table
+    kPhRecord = 3,      // end-of-sweep sums, observables and scheduled refreshes
+    kPhExchange = 4,    // arrival at the device barrier to leaving it (exchange included)
+    kPhTotal = 5,       // the whole walker loop of the launch
+    kPhWindows = 6,     // windows of 64 attempts
+    kPhFlushes = 7,     // windows with at least one flip to apply
+    kPhFlips = 8,       // accepted flips
+    kPhIters = 9,       // guess-and-check iterations of the chain
+    kPhN = 10
+};
+
 // Rigorous per-entry error bounds of a field table (see sweep.hpp): right
 // after a refresh the FP64 sum of at most L couplings is rounded to the
 // table's precision; each flip applied since then adds one rounded coupling
@@ -79,15 +97,16 @@ struct Inst {
     int32_t ev_cap;
     unsigned long long *ctr;   // [kCtrN]
     TableBounds *bnd;          // bounds computed on the device (job kernel)
+    unsigned long long *phase; // [R][kPhN] phase counters, or null (profiling off)
 };
 
 struct Layout {
     size_t J64, J32, spins, h, E, Eerr, nupd, counts, Mw, perm, slot_of, beta, acc6, fatt, facc,
-        xatt, xacc, serE, serM, events, ctr, bnd, T, total;
+        xatt, xacc, serE, serM, events, ctr, bnd, T, phase, total;
 
     static size_t up(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
-    Layout(int L, int q, int R, size_t fbytes, int ser_cap, int ev_cap)
+    Layout(int L, int q, int R, size_t fbytes, int ser_cap, int ev_cap, bool prof = false)
     {
         size_t o = 0;
         auto take = [&](size_t bytes) {
@@ -118,6 +137,7 @@ struct Layout {
         ctr = take(sizeof(unsigned long long) * kCtrN);
         bnd = take(sizeof(TableBounds));
         T = take(sizeof(double) * R);
+        phase = take(prof ? sizeof(unsigned long long) * kPhN * static_cast<size_t>(R) : 0);
         total = o;
     }
 };

@@ -489,7 +489,30 @@ struct ChainRegs {
     double E, Eerr;     // walker energy and its error bound (workgroup-uniform)
     int64_t nupd, nacc; // flips since the last refresh; accepts this sweep (wave 0)
     double eL, errL;    // energy increments held by the accepting lanes (wave 0)
+    uint32_t iters;     // guess-and-check iterations (workgroup-uniform; profiling)
 };
+
+// Phase counters of a walker, kept in thread 0's registers while profiling
+// (see Phase in state.hpp) and added to Inst::phase when the launch ends.
+struct PhaseAcc {
+    uint64_t v[kPhN];
+    uint64_t t;  // clock at the end of the last timed phase
+    bool on;     // thread 0 of a profiled launch
+};
+
+__device__ __forceinline__ void ph_start(PhaseAcc &ph)
+{
+    if (ph.on) ph.t = clock64();
+}
+// Charges the cycles since the last mark to phase k.
+__device__ __forceinline__ void ph_mark(PhaseAcc &ph, int k)
+{
+    if (ph.on) {
+        const uint64_t t = clock64();
+        ph.v[k] += t - ph.t;
+        ph.t = t;
+    }
+}
 
 __device__ __forceinline__ uint64_t lanes_below(int l) { return l >= kWave ? ~0ull : ((1ull << l) - 1ull); }
 
@@ -738,6 +761,7 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
     const double dBd = 2.0 * P.bound_unit;
     const double tfix = kBand + kEvalMargin;
     while (live) {
+        ++cr.iters;
         const uint32_t pk = flip_word(i, a, b, lane);
         // guess: the sure accepts under the current dE
         uint64_t S = ballot(beta * dE + lnu < -(beta * Bd + tfix)) & live;
@@ -1030,22 +1054,32 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
 // LDS (with a doubled coupling row); otherwise the chain takes its energy
 // changes from direct sums over the spins and there is no table to update.
 template <typename F, int QT, bool D>
-__device__ __forceinline__ double sweep_walker(const Inst &P, Walker<F> &W, int w, int64_t n, double beta, ChainRegs &cr)
+__device__ __forceinline__ double sweep_walker(const Inst &P, Walker<F> &W, int w, int64_t n, double beta, ChainRegs &cr,
+                                               PhaseAcc &ph)
 {
     const int L = P.L;
     double part = 0.0;
     int pbuf = 0;
     for (int c0 = 0; c0 < L; c0 += W.chunk) {
         const int cend = min(L, c0 + W.chunk);
+        ph_start(ph);
         gen_draws<F>(P, W, w, n, c0, cend - c0);
         __syncthreads();
+        ph_mark(ph, kPhDraw);
         for (int t0 = c0; t0 < cend; t0 += kWave) {
             chain_window<F, D, !D>(P, W, w, n, beta, t0, c0, cend, cr, pbuf);
             __syncthreads();
+            ph_mark(ph, kPhChain);
             const int np = W.cs->np[(t0 / kWave) & 1];
             if (D && np > 0) {  // without a table in LDS the chain works from direct sums: nothing to flush
                 flush_window<F, QT, D>(P, W, np, part);
                 __syncthreads();
+                ph_mark(ph, kPhFlush);
+                if (ph.on) ++ph.v[kPhFlushes];
+            }
+            if (ph.on) {
+                ++ph.v[kPhWindows];
+                ph.v[kPhFlips] += static_cast<uint64_t>(np);
             }
         }
     }
@@ -1105,12 +1139,16 @@ __global__ __launch_bounds__(kMaxSweepThreads) void k_refresh(Inst P, LdsPlan pl
 // Returns false if the barrier timed out.
 template <typename F, int QT, bool HLDS, bool J64L>
 __device__ __forceinline__ bool run_walker(const Inst &P, const LdsPlan &plan, unsigned char *lds, int w, int64_t n0,
-                                           int32_t nsw, int32_t xevery, int64_t m0, bool fused)
+                                           int32_t nsw, int32_t xevery, int32_t x0, int64_t m0, bool fused)
 {
     const int tid = threadIdx.x;
+    PhaseAcc ph;
+    ph.on = P.phase != nullptr && tid == 0;
+    for (int k = 0; k < kPhN; ++k) ph.v[k] = 0;
+    const uint64_t t_begin = ph.on ? clock64() : 0;
     Walker<F> W = carve<F, HLDS, J64L>(lds, plan, P, w);
     load_walker<F>(P, W, plan, w);
-    ChainRegs cr{P.E[w], P.Eerr[w], P.nupd[w], 0, 0.0, 0.0};
+    ChainRegs cr{P.E[w], P.Eerr[w], P.nupd[w], 0, 0.0, 0.0, 0u};
     int64_t m = m0;
     __syncthreads();
     for (int s = 0; s < nsw; ++s) {
@@ -1118,7 +1156,8 @@ __device__ __forceinline__ bool run_walker(const Inst &P, const LdsPlan &plan, u
         const int slot = __hip_atomic_load(&P.slot_of[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const double beta = P.beta[slot];
         cr.nacc = 0;
-        const double part = sweep_walker<F, QT, HLDS>(P, W, w, n, beta, cr);
+        const double part = sweep_walker<F, QT, HLDS>(P, W, w, n, beta, cr, ph);
+        ph_start(ph);
         // energy change of the sweep: the flush's exact sums (FP32 table in
         // LDS) or the accepted flips' dE held by the chain lanes (FP64 table,
         // or direct sums when there is no table in LDS)
@@ -1141,7 +1180,9 @@ __device__ __forceinline__ bool run_walker(const Inst &P, const LdsPlan &plan, u
             if (tid == 0) atomicAdd(&P.ctr[kCtrRefresh], 1ull);
             __syncthreads();
         }
-        if (fused && xevery > 0 && (s + 1) % xevery == 0) {
+        ph_mark(ph, kPhRecord);
+        // x0: sweeps of the same exchange period done before this launch
+        if (fused && xevery > 0 && (x0 + s + 1) % xevery == 0) {
             for (int j = tid; j < P.L; j += blockDim.x) P.spins[static_cast<size_t>(w) * P.L + j] = W.sp[j];
             if (tid == 0) {
                 P.E[w] = cr.E;
@@ -1156,6 +1197,7 @@ __device__ __forceinline__ bool run_walker(const Inst &P, const LdsPlan &plan, u
             cr.E = __hip_atomic_load(&P.E[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             cr.Eerr = __hip_atomic_load(&P.Eerr[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             ++m;
+            ph_mark(ph, kPhExchange);
         }
     }
     __syncthreads();
@@ -1165,16 +1207,22 @@ __device__ __forceinline__ bool run_walker(const Inst &P, const LdsPlan &plan, u
         P.Eerr[w] = cr.Eerr;
         P.nupd[w] = cr.nupd;
     }
+    if (ph.on) {
+        ph.v[kPhTotal] = clock64() - t_begin;
+        ph.v[kPhIters] = cr.iters;
+        unsigned long long *dst = P.phase + static_cast<size_t>(w) * kPhN;
+        for (int k = 0; k < kPhN; ++k) dst[k] += ph.v[k];
+    }
     __syncthreads();
     return true;
 }
 
 template <typename F, int QT, bool HLDS, bool J64L>
 __global__ __launch_bounds__(kMaxSweepThreads) void k_sweep(Inst P, LdsPlan plan, int64_t n0, int32_t nsw,
-                                                            int32_t xevery, int64_t m0, int32_t fused)
+                                                            int32_t xevery, int32_t x0, int64_t m0, int32_t fused)
 {
     extern __shared__ __align__(16) unsigned char lds[];
-    (void)run_walker<F, QT, HLDS, J64L>(P, plan, lds, blockIdx.x, n0, nsw, xevery, m0, fused != 0);
+    (void)run_walker<F, QT, HLDS, J64L>(P, plan, lds, blockIdx.x, n0, nsw, xevery, x0, m0, fused != 0);
 }
 
 __global__ __launch_bounds__(1024) void k_exchange(Inst P, int64_t m)

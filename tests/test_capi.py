@@ -70,3 +70,57 @@ def test_probe_library_exports():
     text = open(os.path.join(ROOT, "include", "ptmi_probe.h")).read()
     for name in re.findall(r"\b(ptmi_[a-z_]+)\s*\(", text):
         assert hasattr(lib, name)
+
+
+def _checkpoint(L, q, R, spins, perm, prec=0, init=0):
+    """A checkpoint buffer in the library's layout: header, T, spins (0-based),
+    perm, six moment sums and four counter arrays per slot."""
+    import struct
+
+    import numpy as np
+
+    hdr = struct.pack("<IIiiiiiiQdqqq", 0x50544D49, 1, L, q, R, prec, init, 0, 1234, 0.5, 0, 0, 0)
+    T = np.linspace(1.0, 2.0, R).astype("<f8").tobytes()
+    body = (np.asarray(spins, np.uint8).tobytes() + np.asarray(perm, "<i4").tobytes()
+            + np.zeros(6 * R, "<f8").tobytes() + np.zeros(4 * R, "<i8").tobytes())
+    return hdr + T + body
+
+
+@pytest.mark.parametrize("case", ["valid", "spin_equal_q", "spin_255", "perm_duplicate", "perm_range",
+                                  "bad_sizes", "short"])
+def test_load_rejects_corrupt_checkpoint(case):
+    """pt_load checks the buffer on the host before any device call: a spin
+    outside 0..q-1 or a perm that is not a permutation is PT_EINVAL."""
+    import numpy as np
+
+    import paper_1308_5426_amd as pkg
+
+    if not os.path.exists(pkg.LIB_PATH):
+        pytest.skip("library not built")
+    lib = pkg.load_library()
+    L, q, R = 16, 3, 4
+    spins = np.zeros((R, L), np.uint8)
+    perm = np.arange(R)
+    if case == "spin_equal_q":
+        spins[2, 7] = q
+    elif case == "spin_255":
+        spins[0, 0] = 255
+    elif case == "perm_duplicate":
+        perm = np.array([0, 1, 1, 3])
+    elif case == "perm_range":
+        perm = np.array([0, 1, 2, 4])
+    blob = _checkpoint(L, q, R, spins, perm)
+    if case == "bad_sizes":
+        blob = _checkpoint(L, 99, R, spins, perm)
+    if case == "short":
+        blob = blob[:-8]
+    raw = ctypes.create_string_buffer(blob, len(blob))
+    ctx = ctypes.c_void_p()
+    st = lib.pt_load(ctypes.byref(ctx), ctypes.cast(raw, ctypes.c_void_p), len(blob), None)
+    if case == "valid":  # passes the host checks: loads on a GPU, fails at the device without one
+        assert st in (pkg.PT_OK, pkg.PT_EDEVICE), lib.pt_last_error()
+        if st == pkg.PT_OK:
+            assert lib.pt_free(ctx) == pkg.PT_OK
+        return
+    assert st == pkg.PT_EINVAL, lib.pt_last_error()
+    assert not ctx.value

@@ -167,3 +167,35 @@ def test_server_rejects_bad_jobs(pkg):
     with pytest.raises(pkg.PTError):
         srv.submit(dict(L=10, q=3, sigma=0.5, T=np.linspace(0.5, 2.0, 65), seed=1, sweeps=1))
     srv.stop()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_with_largest_job_shapes(pkg, orc, precision):
+    """Jobs at the extremes of the 256-job batched workload (L up to 8192, q up
+    to 10, 32 replicas geometric in [0.2, 3.0]) in one launch at the default
+    shape, each against the oracle on all its walkers."""
+    import workloads
+    from workloads import geometric_ladder
+
+    T = geometric_ladder(0.2, 3.0, 32)
+    jobs = [dict(L=8192, q=10, sigma=0.55, T=T, seed=1234, sweeps=3, exchange_every=1, init=0),
+            dict(L=1000, q=3, sigma=0.4, T=T, seed=1235, sweeps=20, exchange_every=1, init=0),
+            dict(L=128, q=2, sigma=1.0, T=T, seed=1236, sweeps=40, exchange_every=1, init=0)]
+    for j in workloads.batch_jobs(n_jobs=3, sweeps=4):
+        jobs.append(dict(L=j.L, q=j.q, sigma=j.sigma, T=j.T, seed=j.seed, sweeps=j.sweeps, exchange_every=1, init=0))
+    print(f"[batch-large] {[(j['L'], j['q']) for j in jobs]} precision={precision}", flush=True)
+    b = pkg.Batch(jobs, precision=precision)
+    b.run()
+    for j, job in enumerate(jobs):
+        s, p = b.spins(j)
+        obs = b.observables(j)
+        ref = orc.PT(job["L"], job["q"], job["sigma"], job["T"], job["seed"], init=job["init"], mode=0, threads=16)
+        ref.run(job["sweeps"], job["exchange_every"])
+        np.testing.assert_array_equal(s, ref.spins())
+        np.testing.assert_array_equal(p, ref.perm())
+        st = ref.stats()
+        np.testing.assert_array_equal(obs["flip_acc"], st["flip_acc"])
+        np.testing.assert_array_equal(obs["xchg_acc"], st["xchg_acc"])
+        rtol = max(1e-11, job["L"] ** 2 / 2 * 2.0**-53) if not precision else 1e-6
+        np.testing.assert_allclose(obs["E"], ref.energies()[ref.perm()], rtol=rtol)
+    b.close()

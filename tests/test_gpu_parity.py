@@ -129,7 +129,8 @@ def test_small_config_trajectory_fp32(pkg, orc):
     obs = sim.observables()
     E_ref = ref.energies()[ref.perm()]
     np.testing.assert_allclose(obs["E"], E_ref, rtol=1e-6)
-    assert obs["n_recheck"] >= 0
+    print(f"[parity] C1 fp32: {obs['n_recheck']} rechecks, {obs['n_refresh']} refreshes", flush=True)
+    assert obs["n_refresh"] >= 16 * (2000 // 32)  # every walker on the 32-sweep schedule
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -165,13 +166,21 @@ def test_ordered_start_and_extreme_temperatures(pkg, orc):
 
 def test_medium_config_sampled(pkg, orc):
     """L = 1024, q = 3, sigma = 0.4, 64 replicas geometric in [0.3, 3] at its real
-    size and launch shape, for a few sweeps (FP32 and FP64 tables)."""
+    size and launch shape: FP32 table for 40 sweeps (past its 32-sweep refresh,
+    with near-threshold FP64 rechecks), FP64 table for 12 sweeps."""
     T = _ladder(0.3, 3.0, 64)
-    for prec in (1, 0):
-        sim, ref = run_pair(pkg, orc, 1024, 3, 0.4, T, 1234, 12, 1, precision=prec, mode=1, steps=2)
+    for prec, nsw in ((1, 40), (0, 12)):
+        sim, ref = run_pair(pkg, orc, 1024, 3, 0.4, T, 1234, nsw, 1, precision=prec, mode=1, steps=2)
         obs = sim.observables()
         E_ref = ref.energies()[ref.perm()]
         np.testing.assert_allclose(obs["E"], E_ref, rtol=1e-6 if prec else 1e-11)
+        st = ref.stats()
+        np.testing.assert_array_equal(obs["flip_acc"], st["flip_acc"])
+        np.testing.assert_array_equal(obs["xchg_acc"], st["xchg_acc"])
+        if prec:
+            print(f"[parity] C2 fp32: {obs['n_recheck']} rechecks, {obs['n_refresh']} refreshes", flush=True)
+            assert obs["n_recheck"] > 0
+            assert obs["n_refresh"] >= 64
 
 
 def test_checkpoint_resume(pkg, orc):
@@ -200,27 +209,31 @@ def test_invalid_arguments(pkg):
         assert ei.value.status == pkg.PT_EINVAL
 
 
-def test_large_config_sampled(pkg, orc):
+@pytest.mark.parametrize("placement", [0])
+def test_large_config_all_walkers(pkg, orc, placement):
     """L = 16384, q = 5, sigma = 0.3, 128 replicas geometric in [0.2, 2.5], ordered
-    start, FP32 table (too large for LDS, so its rows stay in HBM), at the real
-    launch shape: two sweeps of all walkers; walkers 0, 64 and 127 are followed
-    by the oracle on the same streams."""
+    start, FP32 form, at the real launch shape: three sweeps of every walker with
+    the fused exchange step after each, against the oracle on all walkers."""
     from workloads import large
 
     inst = large()
-    print(f"[parity] large L={inst.L} q={inst.q} R={inst.R}", flush=True)
-    sim = pkg.Simulation(inst.L, inst.q, inst.sigma, inst.T, inst.seed, precision=1, init=inst.init)
-    sim.sweep(2)
+    nsw = 3
+    print(f"[parity] large L={inst.L} q={inst.q} R={inst.R} placement={placement} sweeps={nsw}", flush=True)
+    sim = pkg.Simulation(inst.L, inst.q, inst.sigma, inst.T, inst.seed, precision=1, init=inst.init,
+                         placement=placement)
+    sim.run(nsw, 1)
     s, p = sim.spins()
     obs = sim.observables()
-    np.testing.assert_array_equal(p, np.arange(inst.R))
     ev = sim.events()
-    for w in (0, 64, 127):
-        ref = orc.PT(inst.L, inst.q, inst.sigma, [inst.T[w]], inst.seed, init=inst.init, mode=0, wbase=w)
-        ref.set_replay(met=[(0, b, c, d) for (k, a, b, c, d, _) in ev if k == 0 and a == w])
-        ref.sweep(2)
-        np.testing.assert_array_equal(s[w], ref.spins()[0])
-        # the oracle's initial energy is a sequential sum of L(L-1)/2 terms:
-        # its rounding error is bounded by (L^2/2) 2^-53 |E| (about 1.5e-8 here)
-        assert obs["E"][w] == pytest.approx(ref.energies()[0], rel=inst.L * inst.L / 2 * 2.0**-53)
-        assert obs["flip_acc"][w] == ref.stats()["flip_acc"][0]
+    ref = orc.PT(inst.L, inst.q, inst.sigma, inst.T, inst.seed, init=inst.init, mode=0, threads=16)
+    _replay(ref, ev)
+    ref.run(nsw, 1)
+    np.testing.assert_array_equal(s, ref.spins())
+    np.testing.assert_array_equal(p, ref.perm())
+    st = ref.stats()
+    np.testing.assert_array_equal(obs["flip_acc"], st["flip_acc"])
+    np.testing.assert_array_equal(obs["xchg_att"], st["xchg_att"])
+    np.testing.assert_array_equal(obs["xchg_acc"], st["xchg_acc"])
+    # the oracle's initial energy is a sequential sum of L(L-1)/2 terms: its
+    # rounding error is bounded by (L^2/2) 2^-53 |E| (about 1.5e-8 here)
+    np.testing.assert_allclose(obs["E"], ref.energies()[ref.perm()], rtol=inst.L * inst.L / 2 * 2.0**-53)
