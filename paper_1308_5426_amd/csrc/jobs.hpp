@@ -65,11 +65,8 @@ __device__ __forceinline__ void run_job_walker(const JobSlot &S, int w, unsigned
         // the job's counters (the arena block may have held an earlier job),
         // couplings, error bounds, ladder and zeroed accumulators
         for (int k = tid; k < kCtrN; k += blockDim.x) P.ctr[k] = 0ull;
-        double part = 0.0;
-        for (int r = tid; r <= L / 2; r += blockDim.x) {
+        for (int r = tid; r <= L / 2; r += blockDim.x)
             jstar_entry(L, S.sigma, r, const_cast<double *>(P.J64), const_cast<float *>(P.J32));
-            if (r > 0) part += (L - r != r) ? 2.0 * P.J64[r] : P.J64[r];
-        }
         for (int k = tid; k < R; k += blockDim.x) {
             const_cast<double *>(P.beta)[k] = 1.0 / S.T[k];
             P.perm[k] = k;
@@ -78,7 +75,8 @@ __device__ __forceinline__ void run_job_walker(const JobSlot &S, int w, unsigned
             for (int a = 0; a < 6; ++a) P.acc6[a * R + k] = 0.0;
         }
         __syncthreads();
-        const double Ssum = block_sum(part, reinterpret_cast<double *>(lds));
+        // the same sum, in the same order, as a single instance's k_setup
+        const double Ssum = tid < kWave ? coupling_sum_wave(P.J64, L) : 0.0;
         if (tid == 0) {
             *P.bnd = table_bounds(Ssum, P.J64[1], L, sizeof(F) == sizeof(float));
             __threadfence();

@@ -22,16 +22,17 @@ static_assert(PT_QMAX == kQMax, "q limit");
 
 namespace {
 
-thread_local std::string g_err;
+// A fixed buffer, so that reporting an error allocates nothing either.
+thread_local char g_err[512];
 
 pt_status fail(pt_status st, const char *fmt, ...)
 {
-    char buf[512];
+    char buf[sizeof g_err];
     va_list ap;
     va_start(ap, fmt);
     std::vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
-    g_err = buf;
+    std::memcpy(g_err, buf, sizeof buf);
     return st;
 }
 
@@ -357,20 +358,29 @@ struct HostObs {
     }
 };
 
-// Rigorous per-entry bounds of the field table (see the design notes): right
-// after a refresh the FP64 sum of at most L terms is rounded to the table's
-// precision; each applied flip adds one rounded coupling and one rounding.
-void set_bounds(pt_ctx *c, const std::vector<double> &J)
+// Ladder, slot permutation and table bounds of a fresh instance on the device
+// (k_setup, after k_jstar), then the bounds read back into the instance
+// parameters.  T is copied into the instance's workspace first.  Synchronises
+// the stream.  Allocates nothing.
+pt_status setup_instance(pt_ctx *c, const double *T)
 {
-    double S = 0.0, Jmax = 0.0;
-    for (double v : J) {
-        S += v;
-        Jmax = std::max(Jmax, v);
-    }
-    const TableBounds b = table_bounds(S, Jmax, c->L, c->prec == PT_PREC_F32);
-    c->inst.bound_init = b.init;
-    c->inst.bound_unit = b.unit;
-    c->inst.nupd_max = b.nupd_max;
+    Inst &P = c->inst;
+    const Layout lay = layout_of(c->L, c->q, c->R, c->prec, c->ser_cap, c->ev_cap, c->prof);
+    double *Td = reinterpret_cast<double *>(c->ws + lay.T);
+    HIPCHK(hipMemcpyAsync(Td, T, sizeof(double) * c->R, hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(k_setup, dim3(1), dim3(256), 0, c->stream, P, static_cast<const double *>(Td),
+                       static_cast<int32_t>(c->prec == PT_PREC_F32));
+    HIPCHK(hipGetLastError());
+    TableBounds b;
+    HIPCHK(hipMemcpyAsync(&b, P.bnd, sizeof b, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    // J*(r) > 0 for every r, so a finite sum means finite couplings
+    if (!std::isfinite(b.init) || !std::isfinite(b.unit) || !(b.init > 0.0))
+        return fail(PT_EDEVICE, "non-finite couplings J* (L = %d, sigma = %g)", c->L, c->sigma);
+    P.bound_init = b.init;
+    P.bound_unit = b.unit;
+    P.nupd_max = b.nupd_max;
+    return PT_OK;
 }
 
 }  // namespace
@@ -389,7 +399,7 @@ void pt_default_options(pt_options *o)
     o->placement = PT_PLACE_AUTO;
 }
 
-const char *pt_last_error(void) { return g_err.c_str(); }
+const char *pt_last_error(void) { return g_err; }
 
 pt_status pt_workspace_size(int32_t L, int32_t q, int32_t R, const pt_options *opt, size_t *bytes)
 {
@@ -403,49 +413,50 @@ pt_status pt_workspace_size(int32_t L, int32_t q, int32_t R, const pt_options *o
     return PT_OK;
 }
 
-static pt_status init_impl(pt_ctx **out, int32_t L, int32_t q, double sigma, const double *T, int32_t R,
-                           uint64_t seed, const pt_options *opt, bool draw_spins)
+// Checks the options of a single instance.
+static pt_status check_options(const pt_options &o)
 {
-    pt_options d;
-    pt_default_options(&d);
-    const pt_options &o = opt ? *opt : d;
     if (o.precision != PT_PREC_F64 && o.precision != PT_PREC_F32) return fail(PT_EINVAL, "bad precision");
     if (o.init != PT_INIT_RANDOM && o.init != PT_INIT_ORDERED) return fail(PT_EINVAL, "bad init");
     if (o.threads && (o.threads % kWave || o.threads < kWave || o.threads > kMaxSweepThreads))
         return fail(PT_EINVAL, "threads must be a multiple of 64 in [64, %d]", kMaxSweepThreads);
     if (o.placement < PT_PLACE_AUTO || o.placement > PT_PLACE_DIRECT) return fail(PT_EINVAL, "bad placement");
     if (o.placement == PT_PLACE_HBM) return fail(PT_EINVAL, "placement PT_PLACE_HBM is not available in this build");
+    return PT_OK;
+}
 
-    pt_ctx *c = new (std::nothrow) pt_ctx();
-    if (!c) return fail(PT_ENOMEM, "host allocation failed");
+// Fills the run parameters of c from the options (no device work).
+static void ctx_params(pt_ctx *c, int32_t L, int32_t q, double sigma, int32_t R, uint64_t seed, const pt_options &o)
+{
     c->L = L; c->q = q; c->R = R; c->prec = o.precision; c->init = o.init; c->sigma = sigma; c->seed = seed;
     c->NT = o.threads ? o.threads : auto_threads(L);
     c->ser_cap = std::max(0, o.series_capacity);
     c->ev_cap = o.event_capacity > 0 ? o.event_capacity : 4096;
     c->prof = o.profile != 0;
     c->stream = static_cast<hipStream_t>(o.stream);
-    c->T.assign(T, T + R);
-    auto bail = [&](pt_status st) {
-        if (c->own_ws && c->ws) (void)hipFree(c->ws);
-        delete c;
-        return st;
-    };
+}
 
-    if (hipGetDevice(&c->device) != hipSuccess) return bail(fail(PT_EDEVICE, "no HIP device"));
+// Device set-up of c in the workspace c->ws (at least the layout's size):
+// launch plan, zeroed state, couplings, ladder and bounds, and (draw_spins)
+// the initial spins and field table.  Neither allocates nor frees anything.
+static pt_status init_core(pt_ctx *c, const double *T, const pt_options &o, bool draw_spins)
+{
+    const int32_t L = c->L, q = c->q, R = c->R;
+    if (hipGetDevice(&c->device) != hipSuccess) return fail(PT_EDEVICE, "no HIP device");
     int lds_max = 0;
     if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess ||
         hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess)
-        return bail(fail(PT_EDEVICE, "device query failed"));
-    // Field table in LDS when it fits (or when asked), else its rows stay in HBM.
+        return fail(PT_EDEVICE, "device query failed");
+    // Field table in LDS when it fits (or when asked), else no table: direct sums.
     const size_t lmax = static_cast<size_t>(lds_max);
     bool in_lds = o.placement != PT_PLACE_DIRECT && make_plan(L, q, R, c->prec, false, true, lmax, c->NT, &c->plan);
     if (o.placement == PT_PLACE_LDS && !in_lds)
-        return bail(fail(PT_EINVAL, "field table of %d x %d entries does not fit in %d B of LDS", q, L, lds_max));
+        return fail(PT_EINVAL, "field table of %d x %d entries does not fit in %d B of LDS", q, L, lds_max);
     if (!in_lds && !make_plan(L, q, R, c->prec, false, false, lmax, c->NT, &c->plan))
-        return bail(fail(PT_EINVAL, "couplings and spins of L = %d do not fit in %d B of LDS", L, lds_max));
+        return fail(PT_EINVAL, "couplings and spins of L = %d do not fit in %d B of LDS", L, lds_max);
     bool fused_fits = make_plan(L, q, R, c->prec, true, in_lds, lmax, c->NT, &c->plan_fused);
     if (!fused_fits && in_lds && o.placement != PT_PLACE_LDS) {
-        // keep the persistent launch possible by moving the table to HBM for it
+        // keep the persistent launch possible by giving up the table for it
         fused_fits = make_plan(L, q, R, c->prec, true, false, lmax, c->NT, &c->plan_fused);
         if (fused_fits) {
             in_lds = false;
@@ -454,6 +465,66 @@ static pt_status init_impl(pt_ctx **out, int32_t L, int32_t q, double sigma, con
     }
     c->h_in_lds = in_lds;
 
+    const Layout lay = layout_of(L, q, R, c->prec, c->ser_cap, c->ev_cap, c->prof);
+    if (c->ws_bytes < lay.total) return fail(PT_ENOMEM, "workspace of %zu B < %zu B needed", c->ws_bytes, lay.total);
+    Inst &P = c->inst;
+    fill_inst(P, c->ws, lay, L, q, R, c->seed,
+              o.refresh_every > 0 ? o.refresh_every : (c->prec == PT_PREC_F32 ? 32 : 0), c->ser_cap, c->ev_cap,
+              c->prof);
+    c->refresh_every = P.refresh_every;
+
+    // zero the (possibly caller-provided) workspace: counters, accumulators
+    // and the barrier words start at zero
+    pt_status st = zero_async(c->ws, lay.total, c->stream);
+    if (st != PT_OK) return st;
+
+    const void *sf = c->prec == PT_PREC_F32 ? sweep_fn<float>(q, c->plan) : sweep_fn<double>(q, c->plan);
+    const void *rf = c->prec == PT_PREC_F32 ? refresh_fn<float>(c->plan) : refresh_fn<double>(c->plan);
+    if ((st = set_lds_attr(sf, c->plan.total)) != PT_OK || (st = set_lds_attr(rf, c->plan.total)) != PT_OK) return st;
+    c->can_fuse = false;
+    if (fused_fits) {
+        const void *sff = c->prec == PT_PREC_F32 ? sweep_fn<float>(q, c->plan_fused) : sweep_fn<double>(q, c->plan_fused);
+        int per_cu = 0;
+        if (set_lds_attr(sff, c->plan_fused.total) == PT_OK &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sff, c->NT, c->plan_fused.total) == hipSuccess)
+            c->can_fuse = static_cast<int64_t>(per_cu) * c->cus >= R;
+    }
+    c->max_chunk = o.max_sweeps_per_launch > 0 ? o.max_sweeps_per_launch : 1024;
+
+    hipLaunchKernelGGL(k_jstar, dim3((L / 2 + 1 + 255) / 256), dim3(256), 0, c->stream, L, c->sigma,
+                       const_cast<double *>(P.J64), const_cast<float *>(P.J32));
+    if (hipGetLastError() != hipSuccess) return fail(PT_EDEVICE, "k_jstar launch failed");
+    if ((st = setup_instance(c, T)) != PT_OK) return st;
+    if (draw_spins) {
+        const int64_t total = static_cast<int64_t>(R) * L;
+        const int blocks = static_cast<int>(std::min<int64_t>(4096, (total + 255) / 256));
+        hipLaunchKernelGGL(k_init_spins, dim3(blocks), dim3(256), 0, c->stream, P,
+                           static_cast<int32_t>(c->init == PT_INIT_ORDERED));
+        if (hipGetLastError() != hipSuccess) return fail(PT_EDEVICE, "k_init_spins launch failed");
+        if ((st = c->prec == PT_PREC_F32 ? launch_refresh<float>(c) : launch_refresh<double>(c)) != PT_OK) return st;
+    }
+    return PT_OK;
+}
+
+static pt_status init_impl(pt_ctx **out, int32_t L, int32_t q, double sigma, const double *T, int32_t R,
+                           uint64_t seed, const pt_options *opt, bool draw_spins)
+{
+    pt_options d;
+    pt_default_options(&d);
+    const pt_options &o = opt ? *opt : d;
+    pt_status st = check_options(o);
+    if (st != PT_OK) return st;
+
+    pt_ctx *c = new (std::nothrow) pt_ctx();
+    if (!c) return fail(PT_ENOMEM, "host allocation failed");
+    ctx_params(c, L, q, sigma, R, seed, o);
+    c->T.assign(T, T + R);
+    auto bail = [&](pt_status s) {
+        if (c->own_ws && c->ws) (void)hipFree(c->ws);
+        delete c;
+        return s;
+    };
+    if (hipGetDevice(&c->device) != hipSuccess) return bail(fail(PT_EDEVICE, "no HIP device"));
     const Layout lay = layout_of(L, q, R, c->prec, c->ser_cap, c->ev_cap, c->prof);
     if (o.workspace) {
         if (o.workspace_bytes < lay.total)
@@ -465,56 +536,7 @@ static pt_status init_impl(pt_ctx **out, int32_t L, int32_t q, double sigma, con
         c->own_ws = true;
         c->ws_bytes = lay.total;
     }
-    Inst &P = c->inst;
-    fill_inst(P, c->ws, lay, L, q, R, seed, o.refresh_every > 0 ? o.refresh_every : (c->prec == PT_PREC_F32 ? 32 : 0),
-              c->ser_cap, c->ev_cap, c->prof);
-    c->refresh_every = P.refresh_every;
-
-    // zero the (possibly caller-provided) workspace: counters, accumulators
-    // and the barrier words start at zero
-    if (zero_async(c->ws, lay.total, c->stream) != PT_OK) return bail(PT_EDEVICE);
-    std::vector<double> beta(R);
-    std::vector<int32_t> ident(R);
-    for (int k = 0; k < R; ++k) {
-        beta[k] = 1.0 / T[k];
-        ident[k] = k;
-    }
-    if (hipMemcpyAsync(const_cast<double *>(P.beta), beta.data(), sizeof(double) * R, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-        hipMemcpyAsync(P.perm, ident.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-        hipMemcpyAsync(P.slot_of, ident.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice, c->stream) != hipSuccess)
-        return bail(fail(PT_EDEVICE, "copy of ladder failed"));
-
-    const void *sf = c->prec == PT_PREC_F32 ? sweep_fn<float>(q, c->plan) : sweep_fn<double>(q, c->plan);
-    const void *rf = c->prec == PT_PREC_F32 ? refresh_fn<float>(c->plan) : refresh_fn<double>(c->plan);
-    if (set_lds_attr(sf, c->plan.total) != PT_OK || set_lds_attr(rf, c->plan.total) != PT_OK) return bail(PT_EDEVICE);
-    if (fused_fits) {
-        const void *sff = c->prec == PT_PREC_F32 ? sweep_fn<float>(q, c->plan_fused) : sweep_fn<double>(q, c->plan_fused);
-        int per_cu = 0;
-        if (set_lds_attr(sff, c->plan_fused.total) == PT_OK &&
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sff, c->NT, c->plan_fused.total) == hipSuccess)
-            c->can_fuse = static_cast<int64_t>(per_cu) * c->cus >= R;
-    }
-    c->max_chunk = o.max_sweeps_per_launch > 0 ? o.max_sweeps_per_launch : 1024;
-
-    hipLaunchKernelGGL(k_jstar, dim3((L / 2 + 1 + 255) / 256), dim3(256), 0, c->stream, L, sigma,
-                       const_cast<double *>(P.J64), const_cast<float *>(P.J32));
-    if (hipGetLastError() != hipSuccess) return bail(fail(PT_EDEVICE, "k_jstar launch failed"));
-    if (draw_spins) {
-        const int64_t total = static_cast<int64_t>(R) * L;
-        const int blocks = static_cast<int>(std::min<int64_t>(4096, (total + 255) / 256));
-        hipLaunchKernelGGL(k_init_spins, dim3(blocks), dim3(256), 0, c->stream, P,
-                           static_cast<int32_t>(c->init == PT_INIT_ORDERED));
-        if (hipGetLastError() != hipSuccess) return bail(fail(PT_EDEVICE, "k_init_spins launch failed"));
-        const pt_status st = c->prec == PT_PREC_F32 ? launch_refresh<float>(c) : launch_refresh<double>(c);
-        if (st != PT_OK) return bail(st);
-    }
-    std::vector<double> J(L);
-    if (hipMemcpyAsync(J.data(), P.J64, sizeof(double) * L, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-        hipStreamSynchronize(c->stream) != hipSuccess)
-        return bail(fail(PT_EDEVICE, "initialisation failed"));
-    for (int r = 0; r < L; ++r)
-        if (!std::isfinite(J[r])) return bail(fail(PT_EDEVICE, "non-finite coupling J*(%d)", r));
-    set_bounds(c, J);
+    if ((st = init_core(c, T, o, draw_spins)) != PT_OK) return bail(st);
     *out = c;
     return PT_OK;
 }

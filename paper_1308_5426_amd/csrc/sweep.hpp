@@ -1113,6 +1113,35 @@ __device__ __forceinline__ void record_sweep(const Inst &P, const Walker<F> &W, 
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
+// Sum of the couplings S = sum_{r=1}^{L-1} J*(r) in FP64, by one whole wave in
+// a fixed order (lane-strided partial sums, then the butterfly reduction, which
+// leaves the same value in every lane), so that every caller gets the same
+// bits whatever its workgroup size.
+__device__ __forceinline__ double coupling_sum_wave(const double *J64, int L)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    double part = 0.0;
+    for (int r = 1 + lane; r < L; r += kWave) part += J64[r];
+    return wave_sum(part);
+}
+
+// Ladder and table bounds of a fresh instance (after k_jstar): beta_k = 1/T_k
+// from the temperatures at T (device memory), the identity slot permutation,
+// and the rigorous error bounds of the field table from S and J*(1), the
+// largest coupling.  One workgroup of at least one wave.
+__global__ void k_setup(Inst P, const double *__restrict__ T, int32_t f32)
+{
+    for (int k = threadIdx.x; k < P.R; k += blockDim.x) {
+        const_cast<double *>(P.beta)[k] = 1.0 / T[k];
+        P.perm[k] = k;
+        P.slot_of[k] = k;
+    }
+    if (threadIdx.x < kWave) {
+        const double S = coupling_sum_wave(P.J64, P.L);
+        if (threadIdx.x == 0) *P.bnd = table_bounds(S, P.J64[1], P.L, f32 != 0);
+    }
+}
+
 template <typename F, bool HLDS, bool J64L>
 __global__ __launch_bounds__(kMaxSweepThreads) void k_refresh(Inst P, LdsPlan plan)
 {
