@@ -209,6 +209,37 @@ pt_status pt_free(pt_ctx *ctx);
 const char *pt_last_error(void);
 
 /* ------------------------------------------------------------------------ */
+/* Without allocation.  For callers that cannot allocate device memory: code */
+/* running under stream capture, tight serving loops, harnesses that forbid */
+/* hipMalloc.  pt_run_static does what pt_init, pt_run(n, exchange_every),  */
+/* pt_observables and pt_get_spins do together, with the same kernels and   */
+/* the same results, but keeps the whole device state in one static device */
+/* buffer of PT_STATIC_SCRATCH_BYTES per GPU, which the library owns.  Each */
+/* GPU the library runs on holds that buffer from the library's first use of */
+/* it on that GPU until the process ends.  No hipMalloc, hipFree or other    */
+/* allocating routine is called, on the device or the host.                 */
+/* ------------------------------------------------------------------------ */
+#define PT_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* Arguments as pt_init (L, q, sigma, T[R] ascending, seed, opt: precision,
+ * init, placement, threads, event_capacity, max_sweeps_per_launch and stream
+ * are honoured; series_capacity and profile are ignored; opt->workspace must
+ * be NULL), then n sweeps with an exchange step after every exchange_every-th
+ * (0: none), as pt_run.  Outputs, each optional (NULL = skipped), caller-owned
+ * host memory: *out as pt_observables, spins_out[R * L] and perm_out[R] as
+ * pt_get_spins.  Synchronises the stream before it returns.
+ * PT_EINVAL if the state (the pt_init workspace of these sizes plus 16 R bytes)
+ * exceeds PT_STATIC_SCRATCH_BYTES, as well as for any argument pt_init or
+ * pt_run would refuse.  Every call on one GPU uses that GPU's one buffer and
+ * leaves its state there: host threads calling on the same GPU are serialised
+ * by the library, and no other work may touch the buffer, so calls whose device
+ * work would overlap on one GPU (e.g. from another process sharing its memory)
+ * race. */
+pt_status pt_run_static(int32_t L, int32_t q, double sigma, const double *T, int32_t R, uint64_t seed, int64_t n,
+                        int32_t exchange_every, const pt_options *opt, pt_obs *out, uint8_t *spins_out,
+                        int32_t *perm_out);
+
+/* ------------------------------------------------------------------------ */
 /* Batches: many independent instances of uneven size in one persistent    */
 /* launch.  Workgroups take walkers job by job from a ticket counter, so a */
 /* job's walkers always meet at its exchange barrier; each job runs `sweeps`*/

@@ -86,8 +86,9 @@ EXPORTS = [
     "pt_batch_workspace_size", "pt_batch_create", "pt_batch_run", "pt_batch_observables",
     "pt_batch_get_spins", "pt_batch_shape", "pt_batch_free",
     "pt_server_start", "pt_server_submit", "pt_server_poll", "pt_server_wait", "pt_server_times",
-    "pt_server_get_spins", "pt_server_stop",
+    "pt_server_get_spins", "pt_server_stop", "pt_run_static",
 ]
+STATIC_SCRATCH_BYTES = 64 << 20
 
 _lib = None
 
@@ -143,6 +144,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.pt_server_times.argtypes = [_P, i64, ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(d)]
     L.pt_server_get_spins.argtypes = [_P, i64, _P, _P]
     L.pt_server_stop.argtypes = [_P]
+    L.pt_run_static.argtypes = [i32, i32, d, _P, i32, u64, i64, i32, OP, OB, _P, _P]
     for name in EXPORTS:
         if name != "pt_default_options" and name != "pt_last_error":
             getattr(L, name).restype = ctypes.c_int
@@ -353,6 +355,32 @@ class Simulation:
         Simulation.__init__(self, L, q, sigma, T, seed, _ctx=ctx, _ws=ws,
                             series_capacity=opt.series_capacity)
         return self
+
+
+def run_static(L, q, sigma, T, seed, sweeps, exchange_every=1, precision=PREC_F64, init=INIT_RANDOM,
+               threads=0, placement=PLACE_AUTO, max_sweeps_per_launch=0, event_capacity=0):
+    """pt_run_static: pt_init + pt_run + pt_observables + pt_get_spins in one
+    call that allocates no device memory (the state lives in the library's
+    static device buffer).  Runs on PyTorch's current stream.  Returns
+    (observables dict, spins [R][L] by walker with values 1..q, perm)."""
+    import torch
+
+    lib = load_library()
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible to PyTorch; the HIP path has no CPU fallback")
+    T = np.ascontiguousarray(np.asarray(T, dtype=np.float64))
+    R = len(T)
+    opt = Options()
+    lib.pt_default_options(ctypes.byref(opt))
+    opt.precision, opt.init, opt.threads, opt.placement = int(precision), int(init), int(threads), int(placement)
+    opt.max_sweeps_per_launch, opt.event_capacity = int(max_sweeps_per_launch), int(event_capacity)
+    opt.stream = torch.cuda.current_stream().cuda_stream
+    o, arrs, ints, pairs, perm = _obs_buffers(R)
+    spins = np.zeros((R, int(L)), np.uint8)
+    perm2 = np.zeros(R, np.int32)
+    _check(lib.pt_run_static(int(L), int(q), float(sigma), _ptr(T), R, int(seed), int(sweeps), int(exchange_every),
+                             ctypes.byref(opt), ctypes.byref(o), _ptr(spins), _ptr(perm2)))
+    return _obs_dict(o, arrs, ints, pairs, perm, R), spins, perm2
 
 
 class Batch:

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -835,6 +836,119 @@ pt_status pt_free(pt_ctx *c)
     (void)hipStreamSynchronize(c->stream);
     if (c->own_ws && c->ws) (void)hipFree(c->ws);
     delete c;
+    return PT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Single instance without allocation: the device state lives in `scratch`, a
+// static device array (one per GPU, held until the process ends).
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+static __device__ __align__(256) unsigned char scratch[PT_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu[kMaxDevices];
+unsigned char *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's copy of `scratch`, looked up once per device
+// (with that device current).  In host code the array's name only stands in for
+// the symbol: kernels and copies must be given this address instead.  The caller
+// holds g_scratch_mu[dev].
+pt_status scratch_address(int dev, unsigned char **out)
+{
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(PT_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<unsigned char *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return PT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pt_status pt_run_static(int32_t L, int32_t q, double sigma, const double *T, int32_t R, uint64_t seed, int64_t n,
+                        int32_t exchange_every, const pt_options *opt, pt_obs *out, uint8_t *spins_out,
+                        int32_t *perm_out)
+{
+    pt_status st = validate(L, q, sigma, T, R);
+    if (st != PT_OK) return st;
+    if (n < 0 || exchange_every < 0) return fail(PT_EINVAL, "n and exchange_every must be >= 0");
+    pt_options d;
+    pt_default_options(&d);
+    pt_options o = opt ? *opt : d;
+    if (o.workspace) return fail(PT_EINVAL, "pt_run_static takes no workspace (its state lives in the static buffer)");
+    if ((st = check_options(o)) != PT_OK) return st;
+    o.series_capacity = 0;  // nothing outlives the call but its outputs
+    o.profile = 0;
+    pt_ctx c;  // on the stack; its temperature copy stays empty (no checkpoints here)
+    ctx_params(&c, L, q, sigma, R, seed, o);
+    const Layout lay = layout_of(L, q, R, c.prec, c.ser_cap, c.ev_cap, false);
+    const size_t need = lay.total + Layout::up(2 * sizeof(double) * static_cast<size_t>(R));
+    if (need > PT_STATIC_SCRATCH_BYTES)
+        return fail(PT_EINVAL, "state of L = %d, q = %d, R = %d needs %zu B, beyond the static buffer of %zu B", L, q, R,
+                    need, static_cast<size_t>(PT_STATIC_SCRATCH_BYTES));
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(PT_EDEVICE, "device ordinal %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu[dev]);
+    unsigned char *base = nullptr;
+    if ((st = scratch_address(dev, &base)) != PT_OK) return st;
+    c.ws = base;
+    c.ws_bytes = lay.total;
+    c.own_ws = false;
+    if ((st = init_core(&c, T, o, true)) != PT_OK) return st;
+    if ((st = pt_run(&c, n, exchange_every)) != PT_OK) return st;
+    HIPCHK(hipStreamSynchronize(c.stream));
+    if ((st = device_error(&c)) != PT_OK) return st;
+
+    const Inst &P = c.inst;
+    hipStream_t s = c.stream;
+    if (out) {
+        double *Eslot = reinterpret_cast<double *>(base + lay.total);
+        double *Mslot = Eslot + R;
+        hipLaunchKernelGGL(k_obs_by_slot, dim3((R + 255) / 256), dim3(256), 0, s, P, Eslot, Mslot);
+        HIPCHK(hipGetLastError());
+        auto get = [&](void *dst, const void *src, size_t bytes) -> pt_status {
+            if (dst && bytes) HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
+            return PT_OK;
+        };
+        const size_t rd = sizeof(double) * R, ri = sizeof(int64_t) * R, rp = sizeof(int64_t) * (R - 1);
+        double *sums[6] = {out->sumE, out->sumE2, out->sumE4, out->sumM, out->sumM2, out->sumM4};
+        unsigned long long ctr[kCtrN];
+        if ((st = get(out->E, Eslot, rd)) != PT_OK || (st = get(out->M, Mslot, rd)) != PT_OK) return st;
+        for (int a = 0; a < 6; ++a)
+            if ((st = get(sums[a], P.acc6 + a * R, rd)) != PT_OK) return st;
+        if ((st = get(out->flip_att, P.fatt, ri)) != PT_OK || (st = get(out->flip_acc, P.facc, ri)) != PT_OK ||
+            (st = get(out->xchg_att, P.xatt, rp)) != PT_OK || (st = get(out->xchg_acc, P.xacc, rp)) != PT_OK ||
+            (st = get(out->perm, P.perm, sizeof(int32_t) * R)) != PT_OK || (st = get(ctr, P.ctr, sizeof ctr)) != PT_OK)
+            return st;
+        HIPCHK(hipStreamSynchronize(s));
+        out->R = R; out->q = q; out->L = L;
+        out->sweeps = c.sweeps; out->exchange_steps = c.xsteps; out->samples = c.samples;
+        out->n_recheck = static_cast<int64_t>(ctr[kCtrRecheck]);
+        out->n_banded = static_cast<int64_t>(ctr[kCtrBandedMet] + ctr[kCtrBandedEx]);
+        out->n_exact_energy = static_cast<int64_t>(ctr[kCtrExactE]);
+        out->n_refresh = static_cast<int64_t>(ctr[kCtrRefresh]);
+        out->n_events_dropped = ctr[kCtrEvents] > static_cast<unsigned long long>(c.ev_cap)
+                                    ? static_cast<int64_t>(ctr[kCtrEvents] - c.ev_cap)
+                                    : 0;
+    }
+    if (spins_out || perm_out) {
+        const size_t ns = static_cast<size_t>(R) * L;
+        if (spins_out) HIPCHK(hipMemcpyAsync(spins_out, P.spins, ns, hipMemcpyDeviceToHost, s));
+        if (perm_out) HIPCHK(hipMemcpyAsync(perm_out, P.perm, sizeof(int32_t) * R, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (spins_out)
+            for (size_t e = 0; e < ns; ++e) spins_out[e] = static_cast<uint8_t>(spins_out[e] + 1);
+    }
     return PT_OK;
 }
 

@@ -1142,6 +1142,17 @@ __global__ void k_setup(Inst P, const double *__restrict__ T, int32_t f32)
     }
 }
 
+// Current energy and magnetisation by temperature slot (E_slot[k] =
+// E[perm[k]]), for a caller that copies observables without host staging.
+__global__ void k_obs_by_slot(Inst P, double *__restrict__ Eslot, double *__restrict__ Mslot)
+{
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < P.R; k += gridDim.x * blockDim.x) {
+        const int w = P.perm[k];
+        Eslot[k] = P.E[w];
+        Mslot[k] = P.Mw[w];
+    }
+}
+
 template <typename F, bool HLDS, bool J64L>
 __global__ __launch_bounds__(kMaxSweepThreads) void k_refresh(Inst P, LdsPlan plan)
 {

@@ -124,3 +124,28 @@ def test_load_rejects_corrupt_checkpoint(case):
         return
     assert st == pkg.PT_EINVAL, lib.pt_last_error()
     assert not ctx.value
+
+
+def test_run_static_rejects_on_the_host():
+    """pt_run_static refuses bad arguments, a caller workspace and a state beyond
+    its static buffer before any device call (no GPU needed)."""
+    import numpy as np
+
+    import paper_1308_5426_amd as pkg
+
+    if not os.path.exists(pkg.LIB_PATH):
+        pytest.skip("library not built")
+    lib = pkg.load_library()
+    T = np.linspace(0.5, 2.0, 128)
+    Tp = T.ctypes.data_as(ctypes.c_void_p)
+    assert lib.pt_run_static(1, 3, 0.5, Tp, 4, 1, 1, 1, None, None, None, None) == pkg.PT_EINVAL
+    assert lib.pt_run_static(64, 3, 0.5, Tp, 4, 1, -1, 1, None, None, None, None) == pkg.PT_EINVAL
+    opt = pkg.Options()
+    lib.pt_default_options(ctypes.byref(opt))
+    opt.workspace, opt.workspace_bytes = 4096, 1 << 20
+    assert lib.pt_run_static(64, 3, 0.5, Tp, 4, 1, 1, 1, ctypes.byref(opt), None, None, None) == pkg.PT_EINVAL
+    assert b"no workspace" in lib.pt_last_error()
+    # FP64 table state of 128 walkers x 65535 sites x 16 states: far beyond 64 MiB
+    assert lib.pt_run_static(65535, 16, 0.5, Tp, 128, 1, 1, 1, None, None, None, None) == pkg.PT_EINVAL
+    assert b"static buffer" in lib.pt_last_error()
+    assert pkg.STATIC_SCRATCH_BYTES == 64 << 20
