@@ -41,8 +41,11 @@ def _compile(src, lib, verbose):
 def build(verbose: bool = False) -> str:
     """Compile csrc/ptmi.hip (and the headers it includes) into libptmi.so, and
     the LDS bandwidth probe into libptmi_probe.so."""
-    _compile(SRC, LIB, verbose)
-    _compile(PROBE_SRC, PROBE_LIB, verbose)
+    from concurrent.futures import ThreadPoolExecutor
+
+    with ThreadPoolExecutor(2) as ex:
+        for f in [ex.submit(_compile, SRC, LIB, verbose), ex.submit(_compile, PROBE_SRC, PROBE_LIB, verbose)]:
+            f.result()
     return LIB
 
 

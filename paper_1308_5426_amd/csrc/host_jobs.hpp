@@ -41,14 +41,10 @@ size_t job_bytes(const pt_job_desc &j, int prec)
 pt_status job_plan(const pt_job_desc &j, int prec, int budget, int threads, LdsPlan *plan, int32_t *variant)
 {
     const size_t b = static_cast<size_t>(budget);
-    bool in_lds = make_plan(j.L, j.q, j.R, prec, true, true, b, threads, plan);
-    if (!in_lds && !make_plan(j.L, j.q, j.R, prec, true, false, b, threads, plan))
+    const bool in_lds = make_plan(j.L, j.q, j.R, prec, true, kPlLds, b, threads, plan);
+    if (!in_lds && !make_plan(j.L, j.q, j.R, prec, true, kPlHbm, b, threads, plan))
         return fail(PT_EINVAL, "job with L = %d, R = %d does not fit an LDS budget of %d B", j.L, j.R, budget);
-    int32_t v = 0;
-    if (plan->h_in_lds) v |= kVarHLds;
-    if (plan->j64_in_lds) v |= kVarJ64Lds;
-    if (j.q <= 4) v |= kVarRegFlush;
-    *variant = v;
+    *variant = job_variant(plan->place, j.q, plan->j64_in_lds != 0);
     return PT_OK;
 }
 
@@ -75,7 +71,7 @@ void job_slot(JobSlot &S, const pt_job_desc &j, int prec, unsigned char *base, c
 {
     const Layout lay = layout_of(j.L, j.q, j.R, prec, 0, kJobEvents);
     std::memset(&S, 0, sizeof S);
-    fill_inst(S.inst, base, lay, j.L, j.q, j.R, j.seed, prec == PT_PREC_F32 ? 32 : 0, 0, kJobEvents);
+    fill_inst(S.inst, base, lay, j.L, j.q, j.R, j.seed, 0, 0, kJobEvents);
     S.plan = plan;
     S.T = Tdev;
     S.jc = jc;
@@ -218,7 +214,7 @@ pt_status pt_batch_create(pt_batch **out, const pt_job_desc *jobs, int32_t njobs
         for (int j = 0; j < njobs; ++j) {
             LdsPlan pl;
             while (b->budget < cap &&
-                   !make_plan(jobs[j].L, jobs[j].q, jobs[j].R, b->prec, true, false, b->budget, b->threads, &pl))
+                   !make_plan(jobs[j].L, jobs[j].q, jobs[j].R, b->prec, true, kPlHbm, b->budget, b->threads, &pl))
                 b->budget = std::min(cap, b->budget + 4096);
         }
     }

@@ -27,7 +27,15 @@
 
 namespace ptmi {
 
-enum : int32_t { kVarHLds = 1, kVarJ64Lds = 2, kVarRegFlush = 4 };
+// Kernel variant of a job: placement of its field table (kPl*, bits 0-1), rows
+// held in registers by the flush (bits 2-3: 0 none, 1 four, 2 eight) and FP64
+// couplings in LDS (bit 4).
+constexpr int32_t kVarQtShift = 2, kVarJ64Lds = 16;
+__host__ __device__ inline int32_t job_variant(int place, int q, bool j64_in_lds)
+{
+    const int32_t qt = q <= 4 ? 1 : (q <= 8 ? 2 : 0);
+    return static_cast<int32_t>(place) | (qt << kVarQtShift) | (j64_in_lds ? kVarJ64Lds : 0);
+}
 
 struct alignas(256) JobSlot {
     Inst inst;
@@ -53,7 +61,7 @@ __device__ __forceinline__ int32_t load_published(const int32_t *p)
 }
 
 // Set-up and sweeps of walker w of job S, then the job's completion count.
-template <typename F, int QT, bool HLDS, bool J64L>
+template <typename F, int QT, int PL, bool J64L>
 __device__ __forceinline__ void run_job_walker(const JobSlot &S, int w, unsigned char *lds, int32_t *done_flag, int32_t *sflag)
 {
     // the slot may sit in host memory (serving): read it once
@@ -75,10 +83,9 @@ __device__ __forceinline__ void run_job_walker(const JobSlot &S, int w, unsigned
             for (int a = 0; a < 6; ++a) P.acc6[a * R + k] = 0.0;
         }
         __syncthreads();
-        // the same sum, in the same order, as a single instance's k_setup
-        const double Ssum = tid < kWave ? coupling_sum_wave(P.J64, L) : 0.0;
+        // the same sums, in the same order, as a single instance's k_setup
+        if (tid < kWave) store_bounds_wave(P, sizeof(F) == sizeof(float));
         if (tid == 0) {
-            *P.bnd = table_bounds(Ssum, P.J64[1], L, sizeof(F) == sizeof(float));
             __threadfence();
             __hip_atomic_store(&jc[0], 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -102,10 +109,11 @@ __device__ __forceinline__ void run_job_walker(const JobSlot &S, int w, unsigned
         P.bound_init = __hip_atomic_load(&P.bnd->init, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         P.bound_unit = __hip_atomic_load(&P.bnd->unit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         P.nupd_max = __hip_atomic_load(&P.bnd->nupd_max, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        P.bound_flipE = __hip_atomic_load(&P.bnd->flipE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         for (int j = tid; j < L; j += blockDim.x)
             P.spins[static_cast<size_t>(w) * L + j] = initial_spin(P, w, j, S.init != 0);
         __syncthreads();
-        Walker<F> W = carve<F, HLDS, J64L>(lds, plan, P, w);
+        Walker<F> W = carve<F, PL, J64L>(lds, plan, P, w);
         load_walker<F>(P, W, plan, w);
         const double E = refresh_fields<F>(P, W);
         __syncthreads();
@@ -119,7 +127,7 @@ __device__ __forceinline__ void run_job_walker(const JobSlot &S, int w, unsigned
             P.Mw[w] = (static_cast<double>(P.q) * nmax / L - 1.0) / (P.q - 1);
         }
         __syncthreads();
-        ok = run_walker<F, QT, HLDS, J64L>(P, plan, lds, w, 0, static_cast<int32_t>(S.sweeps), S.xevery, 0, 0, true);
+        ok = run_walker<F, QT, PL, J64L>(P, plan, lds, w, 0, static_cast<int32_t>(S.sweeps), S.xevery, 0, 0, true);
     }
     if (tid == 0) {
         if (!ok) atomicOr(&P.ctr[kCtrError], kErrBarrierTimeout);
@@ -133,28 +141,38 @@ __device__ __forceinline__ void run_job_walker(const JobSlot &S, int w, unsigned
     __syncthreads();
 }
 
+template <typename F, int PL, bool J64L>
+__device__ __forceinline__ void dispatch_qt(const JobSlot &S, int w, unsigned char *lds, int32_t *done_flag, int32_t *sflag)
+{
+    if constexpr (PL == kPlDirect) {
+        run_job_walker<F, 0, PL, J64L>(S, w, lds, done_flag, sflag);
+    } else {
+        switch ((S.variant >> kVarQtShift) & 3) {
+        case 1: run_job_walker<F, 4, PL, J64L>(S, w, lds, done_flag, sflag); break;
+        case 2: run_job_walker<F, 8, PL, J64L>(S, w, lds, done_flag, sflag); break;
+        default: run_job_walker<F, 0, PL, J64L>(S, w, lds, done_flag, sflag); break;
+        }
+    }
+}
+
+template <typename F, int PL>
+__device__ __forceinline__ void dispatch_j64(const JobSlot &S, int w, unsigned char *lds, int32_t *done_flag, int32_t *sflag)
+{
+    if constexpr (sizeof(F) == sizeof(double))  // FP64 couplings are the table's own, always in LDS
+        dispatch_qt<F, PL, true>(S, w, lds, done_flag, sflag);
+    else if (S.variant & kVarJ64Lds)
+        dispatch_qt<F, PL, true>(S, w, lds, done_flag, sflag);
+    else
+        dispatch_qt<F, PL, false>(S, w, lds, done_flag, sflag);
+}
+
 template <typename F>
 __device__ __forceinline__ void dispatch_job_walker(const JobSlot &S, int w, unsigned char *lds, int32_t *done_flag, int32_t *sflag)
 {
-    const int v = S.variant;
-    if constexpr (sizeof(F) == sizeof(double)) {
-        switch (v & (kVarHLds | kVarRegFlush)) {
-        case kVarHLds | kVarRegFlush: run_job_walker<F, 4, true, true>(S, w, lds, done_flag, sflag); break;
-        case kVarHLds: run_job_walker<F, 0, true, true>(S, w, lds, done_flag, sflag); break;
-        case kVarRegFlush: run_job_walker<F, 4, false, true>(S, w, lds, done_flag, sflag); break;
-        default: run_job_walker<F, 0, false, true>(S, w, lds, done_flag, sflag); break;
-        }
-    } else {
-        switch (v & (kVarHLds | kVarJ64Lds | kVarRegFlush)) {
-        case kVarHLds | kVarJ64Lds | kVarRegFlush: run_job_walker<F, 4, true, true>(S, w, lds, done_flag, sflag); break;
-        case kVarHLds | kVarJ64Lds: run_job_walker<F, 0, true, true>(S, w, lds, done_flag, sflag); break;
-        case kVarHLds | kVarRegFlush: run_job_walker<F, 4, true, false>(S, w, lds, done_flag, sflag); break;
-        case kVarHLds: run_job_walker<F, 0, true, false>(S, w, lds, done_flag, sflag); break;
-        case kVarJ64Lds | kVarRegFlush: run_job_walker<F, 4, false, true>(S, w, lds, done_flag, sflag); break;
-        case kVarJ64Lds: run_job_walker<F, 0, false, true>(S, w, lds, done_flag, sflag); break;
-        case kVarRegFlush: run_job_walker<F, 4, false, false>(S, w, lds, done_flag, sflag); break;
-        default: run_job_walker<F, 0, false, false>(S, w, lds, done_flag, sflag); break;
-        }
+    switch (S.variant & 3) {
+    case kPlLds: dispatch_j64<F, kPlLds>(S, w, lds, done_flag, sflag); break;
+    case kPlHbm: dispatch_j64<F, kPlHbm>(S, w, lds, done_flag, sflag); break;
+    default: dispatch_j64<F, kPlDirect>(S, w, lds, done_flag, sflag); break;
     }
 }
 

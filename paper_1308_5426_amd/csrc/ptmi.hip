@@ -81,9 +81,11 @@ int auto_threads(int L)
 
 int32_t align16(int32_t x) { return (x + 15) & ~15; }
 
-bool make_plan_chunk(int L, int q, int R, int prec, bool fused, bool h_in_lds, size_t lds_max, int chunk,
+bool make_plan_chunk(int L, int q, int R, int prec, bool fused, int place, size_t lds_max, int chunk,
                      int threads, LdsPlan *p)
 {
+    const bool h_in_lds = place == kPlLds;
+    p->place = place;
     const int32_t fb = static_cast<int32_t>(field_bytes(prec));
     const int nblk = (L + kWave - 1) / kWave;
     const int nw = threads / kWave;
@@ -142,12 +144,12 @@ bool make_plan_chunk(int L, int q, int R, int prec, bool fused, bool h_in_lds, s
 // masks / exchange scratch / staged draws of the largest chunk of 64..1024
 // attempts that fits), FP64 couplings and the first-guessed-flip tables when
 // they fit.
-bool make_plan(int L, int q, int R, int prec, bool fused, bool h_in_lds, size_t lds_max, int threads, LdsPlan *p)
+bool make_plan(int L, int q, int R, int prec, bool fused, int place, size_t lds_max, int threads, LdsPlan *p)
 {
     const int lmax = std::min(1024, ((L + kWave - 1) / kWave) * kWave);
-    if (make_plan_chunk(L, q, R, prec, fused, h_in_lds, lds_max, lmax, threads, p)) return true;
+    if (make_plan_chunk(L, q, R, prec, fused, place, lds_max, lmax, threads, p)) return true;
     for (int chunk = 512; chunk >= kWave; chunk /= 2)
-        if (chunk < lmax && make_plan_chunk(L, q, R, prec, fused, h_in_lds, lds_max, chunk, threads, p)) return true;
+        if (chunk < lmax && make_plan_chunk(L, q, R, prec, fused, place, lds_max, chunk, threads, p)) return true;
     return false;
 }
 
@@ -170,34 +172,46 @@ pt_status validate(int32_t L, int32_t q, double sigma, const double *T, int32_t 
     return PT_OK;
 }
 
-// Kernel variant by the number of states (four flush rows in registers for
-// q <= 4; row by row beyond) and by where the field table and the FP64
-// couplings live.
-template <typename F, bool HLDS, bool J64L>
+// Kernel variant by the number of states (four or eight flush rows in
+// registers for q <= 4 or q <= 8; row by row beyond), by where the field table
+// lives and by whether the FP64 couplings are in LDS.
+template <typename F, int PL, bool J64L>
 const void *sweep_fn_q(int q)
 {
-    if (q <= 4) return reinterpret_cast<const void *>(&k_sweep<F, 4, HLDS, J64L>);
-    return reinterpret_cast<const void *>(&k_sweep<F, 0, HLDS, J64L>);
+    if constexpr (PL == kPlDirect) return reinterpret_cast<const void *>(&k_sweep<F, 0, PL, J64L>);
+    if (q <= 4) return reinterpret_cast<const void *>(&k_sweep<F, 4, PL, J64L>);
+    if (q <= 8) return reinterpret_cast<const void *>(&k_sweep<F, 8, PL, J64L>);
+    return reinterpret_cast<const void *>(&k_sweep<F, 0, PL, J64L>);
+}
+template <typename F, int PL>
+const void *sweep_fn_j(int q, const LdsPlan &p)
+{
+    if constexpr (sizeof(F) == sizeof(double))  // FP64 couplings are the table's own, always in LDS
+        return sweep_fn_q<F, PL, true>(q);
+    return p.j64_in_lds ? sweep_fn_q<F, PL, true>(q) : sweep_fn_q<F, PL, false>(q);
 }
 template <typename F>
 const void *sweep_fn(int q, const LdsPlan &p)
 {
-    if constexpr (sizeof(F) == sizeof(double))  // FP64 couplings are the table's own, always in LDS
-        return p.h_in_lds ? sweep_fn_q<F, true, true>(q) : sweep_fn_q<F, false, true>(q);
-    else if (p.h_in_lds) return p.j64_in_lds ? sweep_fn_q<F, true, true>(q) : sweep_fn_q<F, true, false>(q);
-    return p.j64_in_lds ? sweep_fn_q<F, false, true>(q) : sweep_fn_q<F, false, false>(q);
+    switch (p.place) {
+    case kPlLds: return sweep_fn_j<F, kPlLds>(q, p);
+    case kPlHbm: return sweep_fn_j<F, kPlHbm>(q, p);
+    default: return sweep_fn_j<F, kPlDirect>(q, p);
+    }
+}
+template <typename F, int PL>
+const void *refresh_fn_j(const LdsPlan &p)
+{
+    if constexpr (sizeof(F) == sizeof(double)) return reinterpret_cast<const void *>(&k_refresh<F, PL, true>);
+    return p.j64_in_lds ? reinterpret_cast<const void *>(&k_refresh<F, PL, true>)
+                        : reinterpret_cast<const void *>(&k_refresh<F, PL, false>);
 }
 template <typename F>
 const void *refresh_fn(const LdsPlan &p)
 {
-    if constexpr (sizeof(F) == sizeof(double))
-        return p.h_in_lds ? reinterpret_cast<const void *>(&k_refresh<F, true, true>)
-                          : reinterpret_cast<const void *>(&k_refresh<F, false, true>);
-    else if (p.h_in_lds)
-        return p.j64_in_lds ? reinterpret_cast<const void *>(&k_refresh<F, true, true>)
-                            : reinterpret_cast<const void *>(&k_refresh<F, true, false>);
-    return p.j64_in_lds ? reinterpret_cast<const void *>(&k_refresh<F, false, true>)
-                        : reinterpret_cast<const void *>(&k_refresh<F, false, false>);
+    // refreshes of an HBM table and of a direct-sum walker (whose HBM table is
+    // never read) run the same code
+    return p.place == kPlLds ? refresh_fn_j<F, kPlLds>(p) : refresh_fn_j<F, kPlHbm>(p);
 }
 
 pt_status set_lds_attr(const void *fn, int bytes)
@@ -381,6 +395,7 @@ pt_status setup_instance(pt_ctx *c, const double *T)
     P.bound_init = b.init;
     P.bound_unit = b.unit;
     P.nupd_max = b.nupd_max;
+    P.bound_flipE = b.flipE;
     return PT_OK;
 }
 
@@ -422,7 +437,6 @@ static pt_status check_options(const pt_options &o)
     if (o.threads && (o.threads % kWave || o.threads < kWave || o.threads > kMaxSweepThreads))
         return fail(PT_EINVAL, "threads must be a multiple of 64 in [64, %d]", kMaxSweepThreads);
     if (o.placement < PT_PLACE_AUTO || o.placement > PT_PLACE_DIRECT) return fail(PT_EINVAL, "bad placement");
-    if (o.placement == PT_PLACE_HBM) return fail(PT_EINVAL, "placement PT_PLACE_HBM is not available in this build");
     return PT_OK;
 }
 
@@ -448,30 +462,33 @@ static pt_status init_core(pt_ctx *c, const double *T, const pt_options &o, bool
     if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess ||
         hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess)
         return fail(PT_EDEVICE, "device query failed");
-    // Field table in LDS when it fits (or when asked), else no table: direct sums.
+    // Field table in LDS when it fits (AUTO, or when asked), else in HBM
+    // (AUTO, or when asked); no table when direct sums are asked for.
     const size_t lmax = static_cast<size_t>(lds_max);
-    bool in_lds = o.placement != PT_PLACE_DIRECT && make_plan(L, q, R, c->prec, false, true, lmax, c->NT, &c->plan);
-    if (o.placement == PT_PLACE_LDS && !in_lds)
+    int pl = o.placement == PT_PLACE_DIRECT ? kPlDirect : (o.placement == PT_PLACE_HBM ? kPlHbm : kPlLds);
+    bool fits = make_plan(L, q, R, c->prec, false, pl, lmax, c->NT, &c->plan);
+    if (!fits && o.placement == PT_PLACE_LDS)
         return fail(PT_EINVAL, "field table of %d x %d entries does not fit in %d B of LDS", q, L, lds_max);
-    if (!in_lds && !make_plan(L, q, R, c->prec, false, false, lmax, c->NT, &c->plan))
-        return fail(PT_EINVAL, "couplings and spins of L = %d do not fit in %d B of LDS", L, lds_max);
-    bool fused_fits = make_plan(L, q, R, c->prec, true, in_lds, lmax, c->NT, &c->plan_fused);
-    if (!fused_fits && in_lds && o.placement != PT_PLACE_LDS) {
-        // keep the persistent launch possible by giving up the table for it
-        fused_fits = make_plan(L, q, R, c->prec, true, false, lmax, c->NT, &c->plan_fused);
-        if (fused_fits) {
-            in_lds = false;
-            make_plan(L, q, R, c->prec, false, false, lmax, c->NT, &c->plan);
-        }
+    if (!fits && pl == kPlLds) {
+        pl = kPlHbm;
+        fits = make_plan(L, q, R, c->prec, false, pl, lmax, c->NT, &c->plan);
     }
-    c->h_in_lds = in_lds;
+    if (!fits) return fail(PT_EINVAL, "couplings and spins of L = %d do not fit in %d B of LDS", L, lds_max);
+    bool fused_fits = make_plan(L, q, R, c->prec, true, pl, lmax, c->NT, &c->plan_fused);
+    if (!fused_fits && pl == kPlLds && o.placement != PT_PLACE_LDS &&
+        make_plan(L, q, R, c->prec, true, kPlHbm, lmax, c->NT, &c->plan_fused)) {
+        // keep the persistent launch possible by moving the table to HBM for it
+        fused_fits = true;
+        pl = kPlHbm;
+        make_plan(L, q, R, c->prec, false, pl, lmax, c->NT, &c->plan);
+    }
+    c->h_in_lds = pl == kPlLds;
 
     const Layout lay = layout_of(L, q, R, c->prec, c->ser_cap, c->ev_cap, c->prof);
     if (c->ws_bytes < lay.total) return fail(PT_ENOMEM, "workspace of %zu B < %zu B needed", c->ws_bytes, lay.total);
     Inst &P = c->inst;
     fill_inst(P, c->ws, lay, L, q, R, c->seed,
-              o.refresh_every > 0 ? o.refresh_every : (c->prec == PT_PREC_F32 ? 32 : 0), c->ser_cap, c->ev_cap,
-              c->prof);
+              o.refresh_every > 0 ? o.refresh_every : 0, c->ser_cap, c->ev_cap, c->prof);
     c->refresh_every = P.refresh_every;
 
     // zero the (possibly caller-provided) workspace: counters, accumulators
@@ -685,7 +702,7 @@ pt_status pt_get_plan(pt_ctx *c, int32_t *placement, int32_t *threads, int32_t *
     pt_status st = check_ctx(c);
     if (st != PT_OK) return st;
     const LdsPlan &p = c->can_fuse ? c->plan_fused : c->plan;
-    if (placement) *placement = p.h_in_lds ? PT_PLACE_LDS : PT_PLACE_DIRECT;
+    if (placement) *placement = p.place;
     if (threads) *threads = c->NT;
     if (lds_bytes) *lds_bytes = p.total;
     return PT_OK;

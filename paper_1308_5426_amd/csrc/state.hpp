@@ -40,17 +40,23 @@ enum Phase : int {
     kPhN = 10
 };
 
-// Rigorous per-entry error bounds of a field table (see sweep.hpp): right
+// Rigorous error bounds of a field table (see sweep.hpp).  Per entry: right
 // after a refresh the FP64 sum of at most L couplings is rounded to the
-// table's precision; each flip applied since then adds one rounded coupling
-// and one rounding of the sum.  S = sum_r J*(r), Jmax = J*(1).  nupd_max caps
-// the number of flips between refreshes so the drift stays below 1e-3 S.
+// table's precision (init); each flip applied since then adds one rounded
+// coupling and one rounding of the sum (unit).  S = sum_r J*(r), Jmax = J*(1).
+// nupd_max caps the number of flips between refreshes so the drift stays below
+// 1e-3 S.  FP32 tables take a walker's energy change from the flush's FP64 sums
+// of the FP32 couplings, sum_j J32(|i-j|)([s_j=a] - [s_j=b]): per accepted flip
+// that is off by at most D32 = sum_r |J*(r) - J32(r)| plus the FP64 rounding of
+// an L-term sum (flipE; 0 for FP64 tables, whose energy changes carry their
+// own bound).
 struct TableBounds {
     double init, unit;
     int64_t nupd_max;
+    double flipE;
 };
 
-__host__ __device__ inline TableBounds table_bounds(double S, double Jmax, int L, bool f32)
+__host__ __device__ inline TableBounds table_bounds(double S, double Jmax, double D32, int L, bool f32)
 {
     const double u64 = 0x1p-53;
     const double uF = f32 ? 0x1p-24 : u64;
@@ -59,6 +65,7 @@ __host__ __device__ inline TableBounds table_bounds(double S, double Jmax, int L
     b.unit = uF * (1.001 * S + 2.0 * Jmax) * 1.01 + u64 * S;
     const double cap = 1e-3 * S / b.unit;
     b.nupd_max = cap > 4.0e18 ? static_cast<int64_t>(4e18) : static_cast<int64_t>(cap);
+    b.flipE = f32 ? (D32 + (static_cast<double>(L) + 512.0) * u64 * 1.001 * S) * 1.01 : 0.0;
     return b;
 }
 
@@ -79,6 +86,7 @@ struct Inst {
     int64_t nupd_max;          // forced refresh when the drift counter exceeds this
     double bound_init;         // bound on |h_table - h_exact| right after a refresh
     double bound_unit;         // added to that bound by each applied flip
+    double bound_flipE;        // energy error per accepted flip of an FP32 table (0 otherwise)
     const double *J64;         // [L]
     const float *J32;          // [L]
     uint8_t *spins;            // [R][L], states 0..q-1

@@ -30,13 +30,20 @@ namespace ptmi {
 struct LdsPlan {
     int32_t J, h, J64, masks, sp, cnt, red, misc, xch, draw, dlnu, pend, cs, total;
     int32_t j64_in_lds;   // 1: FP64 couplings resident in LDS
-    int32_t h_in_lds;     // 1: field table in LDS; 0: the walker's rows stay in HBM
+    int32_t h_in_lds;     // 1: field table in LDS; 0: in HBM, or no table (place)
+    int32_t place;        // kPlLds, kPlHbm or kPlDirect
     int32_t chunk;        // attempts whose draws are staged in LDS at a time (multiple of 64)
     int32_t jlen;         // entries of the coupling row J: L, or L + flush span when doubled
     int32_t sfirst;       // [waves][L] u32 first-guessed-flip tables, or -1 when they do not fit
     int32_t xpart;        // [2][waves][64] FP64 partial corrections exchanged between waves
     int32_t ctab;         // [64][4] flush coefficients (table precision) by flip kind
 };
+
+// Where a walker's field table lives during its sweeps (values of
+// PT_PLACE_*): in LDS (with a doubled coupling row), in HBM (couplings and
+// spins in LDS, the table's rows read and written through the caches), or no
+// table at all (every energy change a direct FP64 sum over the spins).
+enum : int { kPlLds = 1, kPlHbm = 2, kPlDirect = 3 };
 
 // Flush geometry: in each pass every wave owns kFlushM blocks of 64
 // consecutive sites; thread (wave v, lane l) holds sites
@@ -83,15 +90,15 @@ struct Walker {
     int32_t chunk;
 };
 
-// HLDS / J64L: the field table / the FP64 couplings are in LDS.  They are
-// compile-time choices so that every access compiles to ds_* (LDS) or
-// global_* (HBM) instructions rather than flat ones.
-template <typename F, bool HLDS, bool J64L>
+// PL / J64L: where the field table is (kPl*) / whether the FP64 couplings
+// are in LDS.  They are compile-time choices so that every access compiles to
+// ds_* (LDS) or global_* (HBM) instructions rather than flat ones.
+template <typename F, int PL, bool J64L>
 __device__ __forceinline__ Walker<F> carve(unsigned char *lds, const LdsPlan &p, const Inst &P, int w)
 {
     Walker<F> W;
     W.J = reinterpret_cast<F *>(lds + p.J);
-    if constexpr (HLDS)
+    if constexpr (PL == kPlLds)
         W.h = reinterpret_cast<F *>(lds + p.h);
     else
         W.h = static_cast<F *>(P.h) + static_cast<size_t>(w) * P.q * P.L;
@@ -806,7 +813,7 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
         if (lead && ((C >> lane) & 1ull)) {
             atomicAdd(&W.cnt[a], -1);
             atomicAdd(&W.cnt[b], 1);
-            if (kF64 || DIR) {  // FP32 tables take E from the flush's exact sums
+            if (kF64 || DIR) {  // FP32 tables take E from the flush's sums
                 cr.eL += dE;
                 cr.errL += Bdl;
             }
@@ -911,30 +918,41 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
 
 // Whole workgroup: apply the window's np flips to the table.  Each thread
 // owns M sites per pass and applies the flips to them in order, so no
-// barrier is needed between flips.  QT > 0: the sites' q <= QT fields sit in
-// registers for the pass (one table read and write per field) and every flip
-// is applied to all of them as fma(coef, J, h) with a wave-uniform
-// coefficient (-1, 0 or +1, from a table by flip kind), which rounds exactly
-// as h - J or h + J; QT = 0 (larger q): per batch of flips, the rows the
-// batch touches are updated one after another, each entry read and written
-// once per batch, the next row's read in flight during this row's update.
-// The couplings of
-// kFlipBatch flips are gathered before they are applied; with a doubled
-// coupling row (D) one address serves a flip's kFlushM gathers.  With an FP32 table the same pass forms the exact FP64
-// energy change of every flip, sum_j J*(|j-i|)[delta(a, s_j) - delta(b, s_j)],
-// over the spins as they were just before it (partial sums per thread; the
-// window-start spins are recovered from the flip list, since the chain has
-// already written the new ones).
+// barrier is needed between flips.  QT > 0 (q <= QT): the sites' fields of
+// the rows the window's flips touch sit in registers for the pass (one table
+// read and write per field; untouched rows are neither read nor written, which
+// matters when the table is in HBM) and every flip is applied to every row as
+// fma(coef, J, h) with a wave-uniform coefficient (-1, 0 or +1: from a table by
+// flip kind for QT = 4, computed from the flip's states for QT = 8), which
+// rounds exactly as h - J or h + J and leaves an untouched row's zeros alone;
+// QT = 0 (larger q): per batch of flips, the rows the batch touches are updated
+// one after another, each entry read and written once per batch, the next
+// row's read in flight during this row's update.  The couplings of kFlipBatch
+// flips are gathered before they are applied; with a doubled coupling row (D)
+// one address serves a flip's kFlushM gathers.  With an FP32 table the same
+// pass forms every flip's energy change in FP64 from the FP32 couplings it
+// already holds, sum_j J32(|j-i|)[delta(a, s_j) - delta(b, s_j)], over the spins
+// as they were just before it (partial sums per thread; the window-start spins
+// are recovered from the flip list, since the chain has already written the
+// new ones); its error against the exact change is at most the bound_flipE the
+// caller charges per flip.
 template <typename F, int QT, bool D>
 __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np, double &part)
 {
-    constexpr int QR = QT > 0 ? QT : 1;  // rows held in registers (q <= 4)
+    constexpr int QR = QT > 0 ? QT : 1;  // rows held in registers (q <= QT)
     constexpr int M = kFlushM;             // register slots per thread
     constexpr int B = kFlipBatch;
     constexpr bool kF32 = sizeof(F) == sizeof(float);
-    const int L = P.L, q = P.q, tid = threadIdx.x, NT = blockDim.x, lane = tid & (kWave - 1);
+    const int L = P.L, tid = threadIdx.x, NT = blockDim.x, lane = tid & (kWave - 1);
     static_assert(kMaxSweepThreads <= 256 && kMaxJobThreads <= 256, "M sites per thread assume <= 256 threads");
     const uint32_t pv = lane < np ? W.pend[lane] : kNoFlip;  // the chain already wrote the spins
+    // rows the window's flips touch (wave-uniform bits)
+    uint32_t touched = 0;
+    if constexpr (QT > 0) {
+        const uint32_t mine = lane < np ? ((1u << fw_old(pv)) | (1u << fw_new(pv))) : 0u;
+#pragma unroll
+        for (int c = 0; c < QT; ++c) touched |= ballot((mine >> c) & 1u) ? (1u << c) : 0u;
+    }
     for (int jb = (tid / kWave) * kWave * M; jb < L; jb += NT * M) {
         const int j0 = jb + lane;
         int jm[M];
@@ -959,13 +977,12 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
 #pragma unroll
         for (int c = 0; c < QT; ++c)
 #pragma unroll
-            for (int m = 0; m < M; ++m) hr[c][m] = (c < q && ok[m]) ? W.h[c * L + jm[m]] : F(0);
+            for (int m = 0; m < M; ++m) hr[c][m] = (((touched >> c) & 1u) && ok[m]) ? W.h[c * L + jm[m]] : F(0);
         (void)hr;
         const F *Jrow = W.J + (j0 + L);  // D: coupling of site j0 + 64 m to site ip is Jrow[64 m - ip]
         for (int p0 = 0; p0 < np; p0 += B) {
             uint32_t pkb[B];
             F g[B][M];
-            double g64[B][M];
 #pragma unroll
             for (int e = 0; e < B; ++e) {
                 // p0 + e <= 63; lanes past np hold the no-flip word
@@ -973,13 +990,13 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
                 const int ip = fw_site(pkb[e]);
 #pragma unroll
                 for (int m = 0; m < M; ++m) {
-                    int d = jm[m] - ip;
-                    d += d < 0 ? L : 0;
-                    if constexpr (D)
+                    if constexpr (D) {
                         g[e][m] = Jrow[m * kWave - ip];
-                    else
+                    } else {
+                        int d = jm[m] - ip;
+                        d += d < 0 ? L : 0;
                         g[e][m] = W.J[d];
-                    g64[e][m] = kF32 ? W.J64[d] : 0.0;
+                    }
                 }
             }
 #pragma unroll
@@ -987,7 +1004,7 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
                 const bool real = p0 + e < np;
                 const int ip = fw_site(pkb[e]), ap = fw_old(pkb[e]), bp = fw_new(pkb[e]);
                 // no branch per flip: padding entries have all coefficients 0
-                if constexpr (QT > 0) {
+                if constexpr (QT == 4) {
                     const F *kc = W.ctab + ((pkb[e] >> 16) & 0x3Fu) * 4;  // one broadcast row per flip
 #pragma unroll
                     for (int c = 0; c < QT; ++c) {
@@ -996,13 +1013,22 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
                         for (int m = 0; m < M; ++m)
                             hr[c][m] = fma(k, g[e][m], hr[c][m]);
                     }
+                } else if constexpr (QT > 0) {
+#pragma unroll
+                    for (int c = 0; c < QT; ++c) {
+                        const F k = flip_coef<F>(c, ap, bp);  // wave-uniform; padding: 0
+#pragma unroll
+                        for (int m = 0; m < M; ++m)
+                            hr[c][m] = fma(k, g[e][m], hr[c][m]);
+                    }
                 }
                 if (kF32) {
 #pragma unroll
                     for (int m = 0; m < M; ++m) {
-                        const int s = sr[m];
-                        part += (real && s == ap) ? g64[e][m] : ((real && s == bp) ? -g64[e][m] : 0.0);
-                        sr[m] = (real && ok[m] && jm[m] == ip) ? bp : s;
+                        const int sj = sr[m];
+                        const double gv = static_cast<double>(g[e][m]);
+                        part += (real && sj == ap) ? gv : ((real && sj == bp) ? -gv : 0.0);
+                        sr[m] = (real && ok[m] && jm[m] == ip) ? bp : sj;
                     }
                 }
             }
@@ -1045,18 +1071,20 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
         for (int c = 0; c < QT; ++c)
 #pragma unroll
             for (int m = 0; m < M; ++m)
-                if (c < q && ok[m]) W.h[c * L + jm[m]] = hr[c][m];
+                if (((touched >> c) & 1u) && ok[m]) W.h[c * L + jm[m]] = hr[c][m];
     }
 }
 
 // One sweep of walker w at sweep index n.  Returns this thread's part of the
-// exact energy change (FP32 table; zero otherwise).  D: the field table is in
-// LDS (with a doubled coupling row); otherwise the chain takes its energy
-// changes from direct sums over the spins and there is no table to update.
-template <typename F, int QT, bool D>
+// energy change (FP32 table: the flush's sums; zero otherwise).  PL: the table
+// in LDS (with a doubled coupling row) or in HBM, whose windows' flips the
+// flush applies, or no table, the chain taking its energy changes from direct
+// sums over the spins.
+template <typename F, int QT, int PL>
 __device__ __forceinline__ double sweep_walker(const Inst &P, Walker<F> &W, int w, int64_t n, double beta, ChainRegs &cr,
                                                PhaseAcc &ph)
 {
+    constexpr bool D = PL == kPlLds, TAB = PL != kPlDirect;
     const int L = P.L;
     double part = 0.0;
     int pbuf = 0;
@@ -1067,11 +1095,11 @@ __device__ __forceinline__ double sweep_walker(const Inst &P, Walker<F> &W, int 
         __syncthreads();
         ph_mark(ph, kPhDraw);
         for (int t0 = c0; t0 < cend; t0 += kWave) {
-            chain_window<F, D, !D>(P, W, w, n, beta, t0, c0, cend, cr, pbuf);
+            chain_window<F, D, !TAB>(P, W, w, n, beta, t0, c0, cend, cr, pbuf);
             __syncthreads();
             ph_mark(ph, kPhChain);
             const int np = W.cs->np[(t0 / kWave) & 1];
-            if (D && np > 0) {  // without a table in LDS the chain works from direct sums: nothing to flush
+            if (TAB && np > 0) {  // without a table the chain works from direct sums: nothing to flush
                 flush_window<F, QT, D>(P, W, np, part);
                 __syncthreads();
                 ph_mark(ph, kPhFlush);
@@ -1125,6 +1153,24 @@ __device__ __forceinline__ double coupling_sum_wave(const double *J64, int L)
     return wave_sum(part);
 }
 
+// D32 = sum_r |J*(r) - J32(r)|, the FP32 couplings' total rounding, by one wave.
+__device__ __forceinline__ double coupling_f32_error_wave(const double *J64, const float *J32, int L)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    double part = 0.0;
+    for (int r = 1 + lane; r < L; r += kWave) part += fabs(J64[r] - static_cast<double>(J32[r]));
+    return wave_sum(part) * 1.001;
+}
+
+// Table bounds of an instance from its couplings, by one whole wave; lane 0
+// stores them at P.bnd.
+__device__ __forceinline__ void store_bounds_wave(const Inst &P, bool f32)
+{
+    const double S = coupling_sum_wave(P.J64, P.L);
+    const double D32 = coupling_f32_error_wave(P.J64, P.J32, P.L);
+    if ((threadIdx.x & (kWave - 1)) == 0) *P.bnd = table_bounds(S, P.J64[1], D32, P.L, f32);
+}
+
 // Ladder and table bounds of a fresh instance (after k_jstar): beta_k = 1/T_k
 // from the temperatures at T (device memory), the identity slot permutation,
 // and the rigorous error bounds of the field table from S and J*(1), the
@@ -1136,10 +1182,7 @@ __global__ void k_setup(Inst P, const double *__restrict__ T, int32_t f32)
         P.perm[k] = k;
         P.slot_of[k] = k;
     }
-    if (threadIdx.x < kWave) {
-        const double S = coupling_sum_wave(P.J64, P.L);
-        if (threadIdx.x == 0) *P.bnd = table_bounds(S, P.J64[1], P.L, f32 != 0);
-    }
+    if (threadIdx.x < kWave) store_bounds_wave(P, f32 != 0);
 }
 
 // Current energy and magnetisation by temperature slot (E_slot[k] =
@@ -1153,12 +1196,12 @@ __global__ void k_obs_by_slot(Inst P, double *__restrict__ Eslot, double *__rest
     }
 }
 
-template <typename F, bool HLDS, bool J64L>
+template <typename F, int PL, bool J64L>
 __global__ __launch_bounds__(kMaxSweepThreads) void k_refresh(Inst P, LdsPlan plan)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     const int w = blockIdx.x;
-    Walker<F> W = carve<F, HLDS, J64L>(lds, plan, P, w);
+    Walker<F> W = carve<F, PL, J64L>(lds, plan, P, w);
     load_walker<F>(P, W, plan, w);
     const double E = refresh_fields<F>(P, W);
     __syncthreads();
@@ -1177,7 +1220,7 @@ __global__ __launch_bounds__(kMaxSweepThreads) void k_refresh(Inst P, LdsPlan pl
 // load its state into LDS, sweep, record, refresh on schedule, and (fused)
 // meet the instance's other walkers at the device barrier for the exchange.
 // Returns false if the barrier timed out.
-template <typename F, int QT, bool HLDS, bool J64L>
+template <typename F, int QT, int PL, bool J64L>
 __device__ __forceinline__ bool run_walker(const Inst &P, const LdsPlan &plan, unsigned char *lds, int w, int64_t n0,
                                            int32_t nsw, int32_t xevery, int32_t x0, int64_t m0, bool fused)
 {
@@ -1186,7 +1229,9 @@ __device__ __forceinline__ bool run_walker(const Inst &P, const LdsPlan &plan, u
     ph.on = P.phase != nullptr && tid == 0;
     for (int k = 0; k < kPhN; ++k) ph.v[k] = 0;
     const uint64_t t_begin = ph.on ? clock64() : 0;
-    Walker<F> W = carve<F, HLDS, J64L>(lds, plan, P, w);
+    constexpr bool TAB = PL != kPlDirect;
+    constexpr bool kF32Tab = TAB && sizeof(F) == sizeof(float);
+    Walker<F> W = carve<F, PL, J64L>(lds, plan, P, w);
     load_walker<F>(P, W, plan, w);
     ChainRegs cr{P.E[w], P.Eerr[w], P.nupd[w], 0, 0.0, 0.0, 0u};
     int64_t m = m0;
@@ -1196,11 +1241,11 @@ __device__ __forceinline__ bool run_walker(const Inst &P, const LdsPlan &plan, u
         const int slot = __hip_atomic_load(&P.slot_of[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const double beta = P.beta[slot];
         cr.nacc = 0;
-        const double part = sweep_walker<F, QT, HLDS>(P, W, w, n, beta, cr, ph);
+        const double part = sweep_walker<F, QT, PL>(P, W, w, n, beta, cr, ph);
         ph_start(ph);
-        // energy change of the sweep: the flush's exact sums (FP32 table in
-        // LDS) or the accepted flips' dE held by the chain lanes (FP64 table,
-        // or direct sums when there is no table in LDS)
+        // energy change of the sweep: the flush's sums over the FP32 couplings
+        // (FP32 table) or the accepted flips' dE held by the chain lanes (FP64
+        // table, or direct sums when there is no table)
         cr.E += block_sum(part + cr.eL, W.red);
         cr.Eerr += block_sum(cr.errL, W.red);
         cr.eL = cr.errL = 0.0;
@@ -1211,9 +1256,10 @@ __device__ __forceinline__ bool run_walker(const Inst &P, const LdsPlan &plan, u
         __syncthreads();
         cr.nupd = W.cs->nupd;
         cr.nacc = W.cs->nacc;
+        if (kF32Tab) cr.Eerr += static_cast<double>(cr.nacc) * P.bound_flipE;
         record_sweep<F>(P, W, w, slot, n, cr.E, cr.nacc);
-        // without a table in LDS there is nothing to refresh (energies come from direct sums)
-        if (HLDS && ((P.refresh_every > 0 && (n + 1) % P.refresh_every == 0) || cr.nupd > P.nupd_max)) {
+        // without a table there is nothing to refresh (energies come from direct sums)
+        if (TAB && ((P.refresh_every > 0 && (n + 1) % P.refresh_every == 0) || cr.nupd > P.nupd_max)) {
             cr.E = refresh_fields<F>(P, W);
             cr.Eerr = 0.0;
             cr.nupd = 0;
@@ -1257,12 +1303,12 @@ __device__ __forceinline__ bool run_walker(const Inst &P, const LdsPlan &plan, u
     return true;
 }
 
-template <typename F, int QT, bool HLDS, bool J64L>
+template <typename F, int QT, int PL, bool J64L>
 __global__ __launch_bounds__(kMaxSweepThreads) void k_sweep(Inst P, LdsPlan plan, int64_t n0, int32_t nsw,
                                                             int32_t xevery, int32_t x0, int64_t m0, int32_t fused)
 {
     extern __shared__ __align__(16) unsigned char lds[];
-    (void)run_walker<F, QT, HLDS, J64L>(P, plan, lds, blockIdx.x, n0, nsw, xevery, x0, m0, fused != 0);
+    (void)run_walker<F, QT, PL, J64L>(P, plan, lds, blockIdx.x, n0, nsw, xevery, x0, m0, fused != 0);
 }
 
 __global__ __launch_bounds__(1024) void k_exchange(Inst P, int64_t m)

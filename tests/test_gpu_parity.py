@@ -130,7 +130,7 @@ def test_small_config_trajectory_fp32(pkg, orc):
     E_ref = ref.energies()[ref.perm()]
     np.testing.assert_allclose(obs["E"], E_ref, rtol=1e-6)
     print(f"[parity] C1 fp32: {obs['n_recheck']} rechecks, {obs['n_refresh']} refreshes", flush=True)
-    assert obs["n_refresh"] >= 16 * (2000 // 32)  # every walker on the 32-sweep schedule
+    assert obs["n_refresh"] > 0  # the hot walkers' table drift reached its cap
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -166,8 +166,9 @@ def test_ordered_start_and_extreme_temperatures(pkg, orc):
 
 def test_medium_config_sampled(pkg, orc):
     """L = 1024, q = 3, sigma = 0.4, 64 replicas geometric in [0.3, 3] at its real
-    size and launch shape: FP32 table for 40 sweeps (past its 32-sweep refresh,
-    with near-threshold FP64 rechecks), FP64 table for 12 sweeps."""
+    size and launch shape: FP32 table for 40 sweeps (past the hot walkers'
+    drift-driven refreshes, with near-threshold FP64 rechecks), FP64 table for
+    12 sweeps."""
     T = _ladder(0.3, 3.0, 64)
     for prec, nsw in ((1, 40), (0, 12)):
         sim, ref = run_pair(pkg, orc, 1024, 3, 0.4, T, 1234, nsw, 1, precision=prec, mode=1, steps=2)
@@ -180,7 +181,7 @@ def test_medium_config_sampled(pkg, orc):
         if prec:
             print(f"[parity] C2 fp32: {obs['n_recheck']} rechecks, {obs['n_refresh']} refreshes", flush=True)
             assert obs["n_recheck"] > 0
-            assert obs["n_refresh"] >= 64
+            assert obs["n_refresh"] > 0
 
 
 def test_checkpoint_resume(pkg, orc):
@@ -209,11 +210,13 @@ def test_invalid_arguments(pkg):
         assert ei.value.status == pkg.PT_EINVAL
 
 
-@pytest.mark.parametrize("placement", [0])
+@pytest.mark.parametrize("placement", [0, 2, 3])
 def test_large_config_all_walkers(pkg, orc, placement):
     """L = 16384, q = 5, sigma = 0.3, 128 replicas geometric in [0.2, 2.5], ordered
     start, FP32 form, at the real launch shape: three sweeps of every walker with
-    the fused exchange step after each, against the oracle on all walkers."""
+    the fused exchange step after each, against the oracle on all walkers, with
+    the field table in HBM (the automatic choice: it does not fit in LDS) and
+    with direct sums and no table."""
     from workloads import large
 
     inst = large()
@@ -221,6 +224,7 @@ def test_large_config_all_walkers(pkg, orc, placement):
     print(f"[parity] large L={inst.L} q={inst.q} R={inst.R} placement={placement} sweeps={nsw}", flush=True)
     sim = pkg.Simulation(inst.L, inst.q, inst.sigma, inst.T, inst.seed, precision=1, init=inst.init,
                          placement=placement)
+    assert sim.plan()["placement"] == (placement or pkg.PLACE_HBM)
     sim.run(nsw, 1)
     s, p = sim.spins()
     obs = sim.observables()
@@ -234,6 +238,8 @@ def test_large_config_all_walkers(pkg, orc, placement):
     np.testing.assert_array_equal(obs["flip_acc"], st["flip_acc"])
     np.testing.assert_array_equal(obs["xchg_att"], st["xchg_att"])
     np.testing.assert_array_equal(obs["xchg_acc"], st["xchg_acc"])
-    # the oracle's initial energy is a sequential sum of L(L-1)/2 terms: its
-    # rounding error is bounded by (L^2/2) 2^-53 |E| (about 1.5e-8 here)
-    np.testing.assert_allclose(obs["E"], ref.energies()[ref.perm()], rtol=inst.L * inst.L / 2 * 2.0**-53)
+    # direct sums: the oracle's initial energy is a sequential sum of L(L-1)/2
+    # terms, whose rounding error is bounded by (L^2/2) 2^-53 |E| (about 1.5e-8
+    # here); FP32 table: energy changes summed from the FP32 couplings, 1e-6
+    rtol = inst.L * inst.L / 2 * 2.0**-53 if placement == 3 else 1e-6
+    np.testing.assert_allclose(obs["E"], ref.energies()[ref.perm()], rtol=rtol)
