@@ -36,6 +36,9 @@ LDS_BYTES_PER_CLK_CU = 256
 LDS_PEAK = CUS * LDS_BYTES_PER_CLK_CU * CLOCK_HZ  # 157.3 TB/s
 HBM_PEAK = 8.0e12
 PLACE_NAMES = {1: "lds", 2: "hbm", 3: "direct"}
+PRECS = {"f64": 0, "f32": 1, "i32": 2}
+PREC_NAMES = {0: "f64", 1: "f32", 2: "i32"}
+TABLE_NAMES = {0: "fp64", 1: "fp32 + fp64 recheck", 2: "int32 fixed point + fp64 recheck"}
 
 
 def workload(name):
@@ -68,7 +71,7 @@ def algorithmic_bytes(obs, inst, prec, placement):
     (9 L).  No table (direct sums): per attempt one spin and one FP64 coupling
     per site (9 L).  Both: per walker and sweep the energy and magnetisation
     reductions read 5 L; per exchange step 8 R of energies."""
-    fb = 4 if prec == 1 else 8
+    fb = 8 if prec == 0 else 4
     acc = int(obs["flip_acc"].sum())
     attempts = inst.L * inst.R * inst.sweeps
     common = inst.R * inst.sweeps * 5 * inst.L + obs["exchange_steps"] * 8 * inst.R
@@ -84,7 +87,7 @@ def phase_summary(ph, inst, prec, placement):
     kernel) against the LDS peak of one CU."""
     import numpy as np
 
-    fb = 4 if prec == 1 else 8
+    fb = 8 if prec == 0 else 4
     tot = ph["total"].astype(float)
     share = {k: float(ph[k].sum() / tot.sum()) for k in ("draw", "chain", "flush", "record", "exchange")}
     hot = int(np.argmax(ph["flips"]))
@@ -226,7 +229,7 @@ def run_batch(args):
     from paper_1308_5426_amd import autotune
 
     jobs = workloads.batch_jobs(n_jobs=args.jobs, sweeps=args.sweeps or 1000)
-    prec = 1 if args.precision == "f32" else 0
+    prec = PRECS[args.precision]
     jd = [dict(L=j.L, q=j.q, sigma=j.sigma, T=j.T, seed=j.seed, sweeps=j.sweeps, exchange_every=1, init=0)
           for j in jobs]
     threads, lds = (autotune.tune(jd, precision=prec, verbose=True) if args.autotune else (args.threads, args.lds))
@@ -263,7 +266,7 @@ def run_batch(args):
         "metric": "spin-flip attempts/sec (all replicas, batched)",
         "value": attempts * args.steps / el, "unit": "attempts/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if prec else "f64", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": PREC_NAMES[prec], "data": "synthetic",
         "config": {"workload": f"{len(jd)} jobs, L log-uniform [128, 8192], q in 2..10, sigma in [0.1, 1], "
                                f"32 replicas geometric [0.2, 3.0], {jd[0]['sweeps']} sweeps, exchange every sweep",
                    "jobs": len(jd), "walkers": sum(len(j["T"]) for j in jd), "attempts": attempts,
@@ -282,7 +285,7 @@ def run_serve(args):
     import workloads
 
     stream = workloads.serve_stream(rate=args.rate, duration=args.duration)
-    prec = 1 if args.precision == "f32" else 0
+    prec = PRECS[args.precision]
     # synchronise before the server starts: a device-wide synchronisation would
     # wait for the server's resident kernel, which runs until stop()
     torch.cuda.synchronize()
@@ -315,7 +318,7 @@ def run_serve(args):
         "metric": "spin-flip attempts/sec (all replicas, served); p50/p99 time-to-result",
         "value": att / span, "unit": "attempts/s", "n_gpus": 1, "steps": 1, "warmup": 0,
         "ms_per_step": span * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if prec else "f64", "data": "synthetic",
+        "dtype": PREC_NAMES[prec], "data": "synthetic",
         "config": {"workload": f"Poisson {args.rate:g} jobs/s for {args.duration:g} s; L log-uniform [64, 4096], "
                                "q in 2..8, sigma in [0.1, 1], 16-64 replicas, 500-5000 sweeps",
                    "jobs": len(ids), "attempts": att},
@@ -370,7 +373,7 @@ def main():
     ap.add_argument("--arena-gb", type=float, default=16.0, help="serve: device arena")
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--lds", type=int, default=0)
-    ap.add_argument("--precision", default="f64", choices=["f32", "f64"])
+    ap.add_argument("--precision", default="f64", choices=list(PRECS))
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="first copy this many bytes device to device (a kernel of known HBM traffic, "
                          "to calibrate the FETCH_SIZE / WRITE_SIZE counters)")
@@ -407,7 +410,7 @@ def main():
     inst = workload(args.workload)
     if args.sweeps:
         inst.sweeps = args.sweeps
-    prec = 1 if args.precision == "f32" else 0
+    prec = PRECS[args.precision]
     placement = {"auto": 0, "lds": 1, "hbm": 2, "direct": 3}[args.placement]
     # the L = 16384 instance runs in launches of 250 sweeps (progress between them)
     elapsed, tk, obs, plan, one_step = run_gpu(inst, prec, args.steps, args.warmup,
@@ -434,14 +437,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if prec else "f64",
+        "dtype": PREC_NAMES[prec],
         "data": "synthetic",
         "config": {
             "workload": f"L={inst.L} q={inst.q} sigma={inst.sigma} R={inst.R} T geometric "
                         f"[{inst.T[0]:g},{inst.T[-1]:g}] sweeps={inst.sweeps} exchange every sweep "
                         f"{'ordered' if inst.init else 'uniform random'} spins seed={inst.seed}",
             "L": inst.L, "q": inst.q, "sigma": inst.sigma, "replicas": inst.R, "sweeps": inst.sweeps,
-            "field_table": ("fp32 + fp64 recheck" if prec else "fp64") + " in " + PLACE_NAMES[plan["placement"]],
+            "field_table": TABLE_NAMES[prec] + " in " + PLACE_NAMES[plan["placement"]],
             "threads_per_walker": plan["threads"], "lds_bytes_per_walker": plan["lds_bytes"],
         },
         "roofline": {

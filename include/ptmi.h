@@ -53,7 +53,15 @@ typedef enum {
     PT_ESTATE = -4    /* call out of order, or on a freed/failed context */
 } pt_status;
 
-enum { PT_PREC_F64 = 0, PT_PREC_F32 = 1 };
+/* Precision of the field table.  F64: FP64 fields.  F32: FP32 fields with
+ * FP64 rechecks of near-threshold attempts and refreshes when the rounding
+ * drift reaches its cap.  I32: fields as exact int32 sums of couplings
+ * quantised to 2^-k (k as large as keeps every field below 2^31): integer
+ * updates are exact and order-free, so the table never drifts and is never
+ * refreshed; near-threshold attempts (a constant band set by the quantisation)
+ * are rechecked in FP64.  All three take every decision as the FP64 method
+ * would (section 3, eq. 8); energies are tracked within a stated bound. */
+enum { PT_PREC_F64 = 0, PT_PREC_F32 = 1, PT_PREC_I32 = 2 };
 enum { PT_INIT_RANDOM = 0, PT_INIT_ORDERED = 1 };
 /* Placement of a walker's field table during its sweeps: in LDS, in HBM
  * (couplings and spins in LDS), or no table at all (every energy change a
@@ -67,11 +75,11 @@ enum { PT_PLACE_AUTO = 0, PT_PLACE_LDS = 1, PT_PLACE_HBM = 2, PT_PLACE_DIRECT = 
 #define PT_BAND 1e-9
 
 typedef struct {
-    int32_t precision;      /* PT_PREC_F64: FP64 field table; PT_PREC_F32: FP32 table
-                               with FP64 recheck of near-threshold attempts */
+    int32_t precision;      /* PT_PREC_F64, PT_PREC_F32 or PT_PREC_I32 (PT_PLACE_DIRECT
+                               takes F64 or F32: it keeps no table) */
     int32_t init;           /* PT_INIT_RANDOM or PT_INIT_ORDERED (all spins 1) */
     int32_t placement;      /* PT_PLACE_*: where the field table lives during a sweep (AUTO:
-                               LDS when it fits, else no table, direct sums) */
+                               LDS when it fits, else HBM; DIRECT: no table, direct sums) */
     int32_t threads;        /* threads per walker workgroup (multiple of 64, <= 256); 0 = auto
                                (single instance: 64 per 256 sites, at most 256; batch/server: 256) */
     int32_t refresh_every;  /* sweeps between O(L^2) recomputations of the fields; 0 = auto */

@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libptmi.so")
 
 PT_OK, PT_EINVAL, PT_ENOMEM, PT_EDEVICE, PT_ESTATE = 0, -1, -2, -3, -4
-PREC_F64, PREC_F32 = 0, 1
+PREC_F64, PREC_F32, PREC_I32 = 0, 1, 2
 INIT_RANDOM, INIT_ORDERED = 0, 1
 PLACE_AUTO, PLACE_LDS, PLACE_HBM, PLACE_DIRECT = 0, 1, 2, 3
 PHASES = ("draw", "chain", "flush", "record", "exchange", "total", "windows", "flushes", "flips", "iters")
@@ -207,8 +207,9 @@ class Simulation:
     """One parallel-tempering run on the GPU (a pt_ctx).
 
     L sites, q states, coupling exponent sigma, temperature ladder T (ascending;
-    slot k has T[k]), 64-bit seed.  precision PREC_F64 (FP64 field table) or
-    PREC_F32 (FP32 table + FP64 rechecks)."""
+    slot k has T[k]), 64-bit seed.  precision PREC_F64 (FP64 field table),
+    PREC_F32 (FP32 table + FP64 rechecks) or PREC_I32 (exact int32 table of
+    quantised couplings + FP64 rechecks)."""
 
     def __init__(self, L, q, sigma, T, seed, precision=PREC_F64, init=INIT_RANDOM, threads=0,
                  refresh_every=0, series_capacity=0, event_capacity=0, max_sweeps_per_launch=0,

@@ -51,7 +51,12 @@ pt_status job_plan(const pt_job_desc &j, int prec, int budget, int threads, LdsP
 template <typename F>
 const void *jobs_fn() { return reinterpret_cast<const void *>(&k_jobs<F>); }
 
-const void *jobs_fn_prec(int prec) { return prec == PT_PREC_F32 ? jobs_fn<float>() : jobs_fn<double>(); }
+const void *jobs_fn_prec(int prec)
+{
+    if (prec == PT_PREC_F32) return jobs_fn<float>();
+    if (prec == PT_PREC_I32) return jobs_fn<int32_t>();
+    return jobs_fn<double>();
+}
 
 // Resident workgroups of k_jobs for (threads, budget) on this device.
 pt_status jobs_capacity(int prec, int threads, int budget, int *cap)
@@ -143,7 +148,7 @@ namespace {
 pt_status batch_layout(const pt_job_desc *jobs, int32_t n, const pt_options &o, pt_batch *b)
 {
     if (!jobs || n < 1) return fail(PT_EINVAL, "no jobs");
-    if (o.precision != PT_PREC_F64 && o.precision != PT_PREC_F32) return fail(PT_EINVAL, "bad precision");
+    if (!valid_prec(o.precision)) return fail(PT_EINVAL, "bad precision");
     size_t off = 0, nT = 0;
     b->job_off.resize(n);
     for (int j = 0; j < n; ++j) {
@@ -482,7 +487,7 @@ pt_status pt_server_start(pt_server **out, size_t arena_bytes, int32_t max_jobs,
     pt_options d;
     pt_default_options(&d);
     const pt_options &o = opt ? *opt : d;
-    if (o.precision != PT_PREC_F64 && o.precision != PT_PREC_F32) return fail(PT_EINVAL, "bad precision");
+    if (!valid_prec(o.precision)) return fail(PT_EINVAL, "bad precision");
     pt_server *s = new (std::nothrow) pt_server();
     if (!s) return fail(PT_ENOMEM, "host allocation failed");
     auto bail = [&](pt_status st) {

@@ -28,12 +28,12 @@
 namespace ptmi {
 
 // Kernel variant of a job: placement of its field table (kPl*, bits 0-1), rows
-// held in registers by the flush (bits 2-3: 0 none, 1 four, 2 eight) and FP64
-// couplings in LDS (bit 4).
+// held in registers by the flush (bits 2-3: 0 none, 1 four, 2 eight, 3 six)
+// and FP64 couplings in LDS (bit 4).
 constexpr int32_t kVarQtShift = 2, kVarJ64Lds = 16;
 __host__ __device__ inline int32_t job_variant(int place, int q, bool j64_in_lds)
 {
-    const int32_t qt = q <= 4 ? 1 : (q <= 8 ? 2 : 0);
+    const int32_t qt = q <= 4 ? 1 : (q <= 6 ? 3 : (q <= 8 ? 2 : 0));
     return static_cast<int32_t>(place) | (qt << kVarQtShift) | (j64_in_lds ? kVarJ64Lds : 0);
 }
 
@@ -84,7 +84,7 @@ __device__ __forceinline__ void run_job_walker(const JobSlot &S, int w, unsigned
         }
         __syncthreads();
         // the same sums, in the same order, as a single instance's k_setup
-        if (tid < kWave) store_bounds_wave(P, sizeof(F) == sizeof(float));
+        setup_couplings(P, table_prec<F>());
         if (tid == 0) {
             __threadfence();
             __hip_atomic_store(&jc[0], 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -110,6 +110,8 @@ __device__ __forceinline__ void run_job_walker(const JobSlot &S, int w, unsigned
         P.bound_unit = __hip_atomic_load(&P.bnd->unit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         P.nupd_max = __hip_atomic_load(&P.bnd->nupd_max, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         P.bound_flipE = __hip_atomic_load(&P.bnd->flipE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        P.ebound = __hip_atomic_load(&P.bnd->ebound, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        P.qscale = __hip_atomic_load(&P.bnd->qscale, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         for (int j = tid; j < L; j += blockDim.x)
             P.spins[static_cast<size_t>(w) * L + j] = initial_spin(P, w, j, S.init != 0);
         __syncthreads();
@@ -120,7 +122,7 @@ __device__ __forceinline__ void run_job_walker(const JobSlot &S, int w, unsigned
         store_walker<F>(P, W, plan, w);
         if (tid == 0) {
             P.E[w] = E;
-            P.Eerr[w] = 0.0;
+            P.Eerr[w] = P.ebound;
             P.nupd[w] = 0;
             int nmax = 0;
             for (int k = 0; k < P.q; ++k) nmax = max(nmax, W.cnt[k]);
@@ -150,6 +152,7 @@ __device__ __forceinline__ void dispatch_qt(const JobSlot &S, int w, unsigned ch
         switch ((S.variant >> kVarQtShift) & 3) {
         case 1: run_job_walker<F, 4, PL, J64L>(S, w, lds, done_flag, sflag); break;
         case 2: run_job_walker<F, 8, PL, J64L>(S, w, lds, done_flag, sflag); break;
+        case 3: run_job_walker<F, 6, PL, J64L>(S, w, lds, done_flag, sflag); break;
         default: run_job_walker<F, 0, PL, J64L>(S, w, lds, done_flag, sflag); break;
         }
     }
@@ -158,8 +161,10 @@ __device__ __forceinline__ void dispatch_qt(const JobSlot &S, int w, unsigned ch
 template <typename F, int PL>
 __device__ __forceinline__ void dispatch_j64(const JobSlot &S, int w, unsigned char *lds, int32_t *done_flag, int32_t *sflag)
 {
-    if constexpr (sizeof(F) == sizeof(double))  // FP64 couplings are the table's own, always in LDS
+    if constexpr (table_prec<F>() == kPrecF64)  // FP64 couplings are the table's own, always in LDS
         dispatch_qt<F, PL, true>(S, w, lds, done_flag, sflag);
+    else if constexpr (table_prec<F>() == kPrecI32)  // never in LDS
+        dispatch_qt<F, PL, false>(S, w, lds, done_flag, sflag);
     else if (S.variant & kVarJ64Lds)
         dispatch_qt<F, PL, true>(S, w, lds, done_flag, sflag);
     else
@@ -172,7 +177,9 @@ __device__ __forceinline__ void dispatch_job_walker(const JobSlot &S, int w, uns
     switch (S.variant & 3) {
     case kPlLds: dispatch_j64<F, kPlLds>(S, w, lds, done_flag, sflag); break;
     case kPlHbm: dispatch_j64<F, kPlHbm>(S, w, lds, done_flag, sflag); break;
-    default: dispatch_j64<F, kPlDirect>(S, w, lds, done_flag, sflag); break;
+    default:  // batches plan LDS or HBM tables; direct sums are no int form
+        if constexpr (table_prec<F>() != kPrecI32) dispatch_j64<F, kPlDirect>(S, w, lds, done_flag, sflag);
+        break;
     }
 }
 

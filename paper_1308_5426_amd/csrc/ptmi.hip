@@ -70,7 +70,9 @@ struct pt_ctx {
 
 namespace {
 
-size_t field_bytes(int prec) { return prec == PT_PREC_F32 ? sizeof(float) : sizeof(double); }
+size_t field_bytes(int prec) { return prec == PT_PREC_F64 ? sizeof(double) : 4; }
+
+bool valid_prec(int prec) { return prec == PT_PREC_F64 || prec == PT_PREC_F32 || prec == PT_PREC_I32; }
 
 // One wave per 256 sites, up to one wave per SIMD.
 int auto_threads(int L)
@@ -120,7 +122,8 @@ bool make_plan_chunk(int L, int q, int R, int prec, bool fused, int place, size_
     if (prec == PT_PREC_F64) {
         p->J64 = p->J;
         p->j64_in_lds = 1;
-    } else if (static_cast<size_t>(o) + 8u * L <= lds_max) {
+    } else if (prec == PT_PREC_F32 && static_cast<size_t>(o) + 8u * L <= lds_max) {
+        // (int tables recheck rarely: their FP64 couplings stay in HBM)
         p->J64 = o;
         o = align16(o + 8 * L);
         p->j64_in_lds = 1;
@@ -172,23 +175,27 @@ pt_status validate(int32_t L, int32_t q, double sigma, const double *T, int32_t 
     return PT_OK;
 }
 
-// Kernel variant by the number of states (four or eight flush rows in
-// registers for q <= 4 or q <= 8; row by row beyond), by where the field table
+// Kernel variant by the number of states (four, six or eight flush rows in
+// registers for q <= 4, 6 or 8; row by row beyond), by where the field table
 // lives and by whether the FP64 couplings are in LDS.
 template <typename F, int PL, bool J64L>
 const void *sweep_fn_q(int q)
 {
     if constexpr (PL == kPlDirect) return reinterpret_cast<const void *>(&k_sweep<F, 0, PL, J64L>);
     if (q <= 4) return reinterpret_cast<const void *>(&k_sweep<F, 4, PL, J64L>);
+    if (q <= 6) return reinterpret_cast<const void *>(&k_sweep<F, 6, PL, J64L>);
     if (q <= 8) return reinterpret_cast<const void *>(&k_sweep<F, 8, PL, J64L>);
     return reinterpret_cast<const void *>(&k_sweep<F, 0, PL, J64L>);
 }
 template <typename F, int PL>
 const void *sweep_fn_j(int q, const LdsPlan &p)
 {
-    if constexpr (sizeof(F) == sizeof(double))  // FP64 couplings are the table's own, always in LDS
+    if constexpr (table_prec<F>() == kPrecF64)  // FP64 couplings are the table's own, always in LDS
         return sweep_fn_q<F, PL, true>(q);
-    return p.j64_in_lds ? sweep_fn_q<F, PL, true>(q) : sweep_fn_q<F, PL, false>(q);
+    else if constexpr (table_prec<F>() == kPrecI32)  // never in LDS
+        return sweep_fn_q<F, PL, false>(q);
+    else
+        return p.j64_in_lds ? sweep_fn_q<F, PL, true>(q) : sweep_fn_q<F, PL, false>(q);
 }
 template <typename F>
 const void *sweep_fn(int q, const LdsPlan &p)
@@ -196,15 +203,19 @@ const void *sweep_fn(int q, const LdsPlan &p)
     switch (p.place) {
     case kPlLds: return sweep_fn_j<F, kPlLds>(q, p);
     case kPlHbm: return sweep_fn_j<F, kPlHbm>(q, p);
-    default: return sweep_fn_j<F, kPlDirect>(q, p);
+    default:
+        if constexpr (table_prec<F>() == kPrecI32) return nullptr;  // no table: not an int form
+        else return sweep_fn_j<F, kPlDirect>(q, p);
     }
 }
 template <typename F, int PL>
 const void *refresh_fn_j(const LdsPlan &p)
 {
-    if constexpr (sizeof(F) == sizeof(double)) return reinterpret_cast<const void *>(&k_refresh<F, PL, true>);
-    return p.j64_in_lds ? reinterpret_cast<const void *>(&k_refresh<F, PL, true>)
-                        : reinterpret_cast<const void *>(&k_refresh<F, PL, false>);
+    if constexpr (table_prec<F>() == kPrecF64) return reinterpret_cast<const void *>(&k_refresh<F, PL, true>);
+    else if constexpr (table_prec<F>() == kPrecI32) return reinterpret_cast<const void *>(&k_refresh<F, PL, false>);
+    else
+        return p.j64_in_lds ? reinterpret_cast<const void *>(&k_refresh<F, PL, true>)
+                            : reinterpret_cast<const void *>(&k_refresh<F, PL, false>);
 }
 template <typename F>
 const void *refresh_fn(const LdsPlan &p)
@@ -214,33 +225,45 @@ const void *refresh_fn(const LdsPlan &p)
     return p.place == kPlLds ? refresh_fn_j<F, kPlLds>(p) : refresh_fn_j<F, kPlHbm>(p);
 }
 
+const void *sweep_fn_prec(int prec, int q, const LdsPlan &p)
+{
+    if (prec == PT_PREC_F32) return sweep_fn<float>(q, p);
+    if (prec == PT_PREC_I32) return sweep_fn<int32_t>(q, p);
+    return sweep_fn<double>(q, p);
+}
+const void *refresh_fn_prec(int prec, const LdsPlan &p)
+{
+    if (prec == PT_PREC_F32) return refresh_fn<float>(p);
+    if (prec == PT_PREC_I32) return refresh_fn<int32_t>(p);
+    return refresh_fn<double>(p);
+}
+
 pt_status set_lds_attr(const void *fn, int bytes)
 {
     HIPCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
     return PT_OK;
 }
 
-template <typename F>
 pt_status launch_refresh(pt_ctx *c)
 {
     Inst P = c->inst;
     LdsPlan plan = c->plan;
     void *args[] = {&P, &plan};
-    HIPCHK(hipLaunchKernel(refresh_fn<F>(plan), dim3(c->R), dim3(c->NT), args, plan.total, c->stream));
+    HIPCHK(hipLaunchKernel(refresh_fn_prec(c->prec, plan), dim3(c->R), dim3(c->NT), args, plan.total, c->stream));
     return PT_OK;
 }
 
-template <typename F>
 pt_status launch_sweep(pt_ctx *c, int64_t n0, int32_t nsw, int32_t xevery, int32_t x0, int64_t m0, bool fused)
 {
     Inst P = c->inst;
     LdsPlan plan = fused ? c->plan_fused : c->plan;
     int32_t fu = fused ? 1 : 0;
     void *args[] = {&P, &plan, &n0, &nsw, &xevery, &x0, &m0, &fu};
+    const void *fn = sweep_fn_prec(c->prec, c->q, plan);
     if (fused)
-        HIPCHK(hipLaunchCooperativeKernel(sweep_fn<F>(c->q, plan), dim3(c->R), dim3(c->NT), args, plan.total, c->stream));
+        HIPCHK(hipLaunchCooperativeKernel(fn, dim3(c->R), dim3(c->NT), args, plan.total, c->stream));
     else
-        HIPCHK(hipLaunchKernel(sweep_fn<F>(c->q, plan), dim3(c->R), dim3(c->NT), args, plan.total, c->stream));
+        HIPCHK(hipLaunchKernel(fn, dim3(c->R), dim3(c->NT), args, plan.total, c->stream));
     return PT_OK;
 }
 
@@ -294,6 +317,7 @@ void fill_inst(Inst &P, unsigned char *b, const Layout &lay, int L, int q, int R
     P.ser_cap = ser_cap;
     P.J64 = reinterpret_cast<const double *>(b + lay.J64);
     P.J32 = reinterpret_cast<const float *>(b + lay.J32);
+    P.Jq = reinterpret_cast<const int32_t *>(b + lay.Jq);
     P.spins = b + lay.spins;
     P.h = b + lay.h;
     P.E = reinterpret_cast<double *>(b + lay.E);
@@ -384,7 +408,7 @@ pt_status setup_instance(pt_ctx *c, const double *T)
     double *Td = reinterpret_cast<double *>(c->ws + lay.T);
     HIPCHK(hipMemcpyAsync(Td, T, sizeof(double) * c->R, hipMemcpyHostToDevice, c->stream));
     hipLaunchKernelGGL(k_setup, dim3(1), dim3(256), 0, c->stream, P, static_cast<const double *>(Td),
-                       static_cast<int32_t>(c->prec == PT_PREC_F32));
+                       static_cast<int32_t>(c->prec));
     HIPCHK(hipGetLastError());
     TableBounds b;
     HIPCHK(hipMemcpyAsync(&b, P.bnd, sizeof b, hipMemcpyDeviceToHost, c->stream));
@@ -396,6 +420,8 @@ pt_status setup_instance(pt_ctx *c, const double *T)
     P.bound_unit = b.unit;
     P.nupd_max = b.nupd_max;
     P.bound_flipE = b.flipE;
+    P.ebound = b.ebound;
+    P.qscale = b.qscale;
     return PT_OK;
 }
 
@@ -432,7 +458,9 @@ pt_status pt_workspace_size(int32_t L, int32_t q, int32_t R, const pt_options *o
 // Checks the options of a single instance.
 static pt_status check_options(const pt_options &o)
 {
-    if (o.precision != PT_PREC_F64 && o.precision != PT_PREC_F32) return fail(PT_EINVAL, "bad precision");
+    if (!valid_prec(o.precision)) return fail(PT_EINVAL, "bad precision");
+    if (o.precision == PT_PREC_I32 && o.placement == PT_PLACE_DIRECT)
+        return fail(PT_EINVAL, "direct sums keep no table: not an int32 form (use FP64 or FP32)");
     if (o.init != PT_INIT_RANDOM && o.init != PT_INIT_ORDERED) return fail(PT_EINVAL, "bad init");
     if (o.threads && (o.threads % kWave || o.threads < kWave || o.threads > kMaxSweepThreads))
         return fail(PT_EINVAL, "threads must be a multiple of 64 in [64, %d]", kMaxSweepThreads);
@@ -496,12 +524,12 @@ static pt_status init_core(pt_ctx *c, const double *T, const pt_options &o, bool
     pt_status st = zero_async(c->ws, lay.total, c->stream);
     if (st != PT_OK) return st;
 
-    const void *sf = c->prec == PT_PREC_F32 ? sweep_fn<float>(q, c->plan) : sweep_fn<double>(q, c->plan);
-    const void *rf = c->prec == PT_PREC_F32 ? refresh_fn<float>(c->plan) : refresh_fn<double>(c->plan);
+    const void *sf = sweep_fn_prec(c->prec, q, c->plan);
+    const void *rf = refresh_fn_prec(c->prec, c->plan);
     if ((st = set_lds_attr(sf, c->plan.total)) != PT_OK || (st = set_lds_attr(rf, c->plan.total)) != PT_OK) return st;
     c->can_fuse = false;
     if (fused_fits) {
-        const void *sff = c->prec == PT_PREC_F32 ? sweep_fn<float>(q, c->plan_fused) : sweep_fn<double>(q, c->plan_fused);
+        const void *sff = sweep_fn_prec(c->prec, q, c->plan_fused);
         int per_cu = 0;
         if (set_lds_attr(sff, c->plan_fused.total) == PT_OK &&
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sff, c->NT, c->plan_fused.total) == hipSuccess)
@@ -519,7 +547,7 @@ static pt_status init_core(pt_ctx *c, const double *T, const pt_options &o, bool
         hipLaunchKernelGGL(k_init_spins, dim3(blocks), dim3(256), 0, c->stream, P,
                            static_cast<int32_t>(c->init == PT_INIT_ORDERED));
         if (hipGetLastError() != hipSuccess) return fail(PT_EDEVICE, "k_init_spins launch failed");
-        if ((st = c->prec == PT_PREC_F32 ? launch_refresh<float>(c) : launch_refresh<double>(c)) != PT_OK) return st;
+        if ((st = launch_refresh(c)) != PT_OK) return st;
     }
     return PT_OK;
 }
@@ -576,8 +604,7 @@ pt_status pt_sweep(pt_ctx *c, int64_t n)
     if (n < 0) return fail(PT_EINVAL, "n < 0");
     while (n > 0) {
         const int32_t chunk = static_cast<int32_t>(std::min<int64_t>(n, c->max_chunk));
-        st = c->prec == PT_PREC_F32 ? launch_sweep<float>(c, c->sweeps, chunk, 0, 0, c->xsteps, false)
-                                    : launch_sweep<double>(c, c->sweeps, chunk, 0, 0, c->xsteps, false);
+        st = launch_sweep(c, c->sweeps, chunk, 0, 0, c->xsteps, false);
         if (st != PT_OK) return st;
         c->sweeps += chunk;
         c->samples += chunk;
@@ -616,9 +643,7 @@ pt_status pt_run(pt_ctx *c, int64_t n, int32_t every)
         const int64_t chunk = std::min<int64_t>(n - done, c->max_chunk);
         const int32_t x0 = static_cast<int32_t>(done % every);  // sweeps of the current period already run
         const int64_t nx = (x0 + chunk) / every;                 // exchange steps inside this launch
-        st = c->prec == PT_PREC_F32
-                 ? launch_sweep<float>(c, c->sweeps, static_cast<int32_t>(chunk), every, x0, c->xsteps, true)
-                 : launch_sweep<double>(c, c->sweeps, static_cast<int32_t>(chunk), every, x0, c->xsteps, true);
+        st = launch_sweep(c, c->sweeps, static_cast<int32_t>(chunk), every, x0, c->xsteps, true);
         if (st != PT_OK) return st;
         c->sweeps += chunk;
         c->samples += chunk;
@@ -793,7 +818,7 @@ pt_status pt_load(pt_ctx **out, const void *buf, size_t len, const pt_options *o
     std::memcpy(T.data(), p, sizeof(double) * R); p += sizeof(double) * R;
     pt_status st = validate(L, hd.q, hd.sigma, T.data(), R);
     if (st != PT_OK) return st;
-    if (hd.prec != PT_PREC_F64 && hd.prec != PT_PREC_F32) return fail(PT_EINVAL, "corrupt checkpoint: precision");
+    if (!valid_prec(hd.prec)) return fail(PT_EINVAL, "corrupt checkpoint: precision");
     if (hd.init != PT_INIT_RANDOM && hd.init != PT_INIT_ORDERED) return fail(PT_EINVAL, "corrupt checkpoint: init");
     if (hd.sweeps < 0 || hd.xsteps < 0 || hd.samples < 0) return fail(PT_EINVAL, "corrupt checkpoint: counters");
     // every spin a state 0..q-1 and perm a permutation of 0..R-1, checked on
@@ -837,7 +862,7 @@ pt_status pt_load(pt_ctx **out, const void *buf, size_t len, const pt_options *o
             return fail_free(fail(PT_EDEVICE, "copy failed"));
         p += sizeof(int64_t) * R;
     }
-    st = c->prec == PT_PREC_F32 ? launch_refresh<float>(c) : launch_refresh<double>(c);
+    st = launch_refresh(c);
     if (st != PT_OK) return fail_free(st);
     if (hipStreamSynchronize(c->stream) != hipSuccess) return fail_free(fail(PT_EDEVICE, "refresh failed"));
     c->sweeps = hd.sweeps;

@@ -40,32 +40,63 @@ enum Phase : int {
     kPhN = 10
 };
 
-// Rigorous error bounds of a field table (see sweep.hpp).  Per entry: right
-// after a refresh the FP64 sum of at most L couplings is rounded to the
-// table's precision (init); each flip applied since then adds one rounded
-// coupling and one rounding of the sum (unit).  S = sum_r J*(r), Jmax = J*(1).
-// nupd_max caps the number of flips between refreshes so the drift stays below
-// 1e-3 S.  FP32 tables take a walker's energy change from the flush's FP64 sums
-// of the FP32 couplings, sum_j J32(|i-j|)([s_j=a] - [s_j=b]): per accepted flip
-// that is off by at most D32 = sum_r |J*(r) - J32(r)| plus the FP64 rounding of
-// an L-term sum (flipE; 0 for FP64 tables, whose energy changes carry their
-// own bound).
+// Table precisions (values of PT_PREC_*).
+enum : int { kPrecF64 = 0, kPrecF32 = 1, kPrecI32 = 2 };
+
+// Rigorous error bounds of a field table (see sweep.hpp), in table units
+// (the real value of a table entry is entry * qscale).  Per entry: right after
+// a refresh the table holds the sum of at most L couplings in its precision,
+// off the exact field by at most init; each flip applied since then adds one
+// rounded coupling and one rounding of the sum (unit).  nupd_max caps the
+// number of flips between refreshes so the drift stays below 1e-3 S.  The
+// walker's tracked energy is off the exact one by at most ebound (real units)
+// right after a refresh, plus flipE per accepted flip; FP64 tables instead add
+// the chain's own bound of each accepted energy change.
+//   FP64: FP64 couplings summed in FP64.
+//   FP32: FP32 couplings J32 summed in FP64 (so the table holds the FP32
+//         couplings' fields, off the exact ones by at most D32 = sum_r |J*(r) -
+//         J32(r)| plus rounding), and energies from sums of J32: the energy of
+//         the J32 couplings, off the exact one by at most L D32 / 2.
+//   I32:  couplings quantised to integers Jq(r) = rint(J*(r) 2^k), k the
+//         largest with S 2^k + L < 2^31 - 2 (so no field overflows), qscale =
+//         2^-k; integer sums and updates are exact, so the table holds the
+//         quantised couplings' fields exactly: off the exact fields by at most
+//         Dq = sum_r |J*(r) - Jq(r) 2^-k|, with no drift and no refresh; the
+//         energy, tracked exactly in the quantised couplings, is off by at
+//         most L Dq / 2.
+// S = sum_r J*(r), Jmax = J*(1).
 struct TableBounds {
     double init, unit;
     int64_t nupd_max;
-    double flipE;
+    double flipE, ebound, qscale;
 };
 
-__host__ __device__ inline TableBounds table_bounds(double S, double Jmax, double D32, int L, bool f32)
+__host__ __device__ inline TableBounds table_bounds(double S, double Jmax, double D32, double Dq, int L, int prec,
+                                                    double qscale)
 {
-    const double u64 = 0x1p-53;
-    const double uF = f32 ? 0x1p-24 : u64;
+    const double u64 = 0x1p-53, Ld = static_cast<double>(L);
     TableBounds b;
-    b.init = (uF * S + (static_cast<double>(L) + 4.0) * u64 * S) * 1.01 + 1e-15 * S;
+    b.qscale = 1.0;
+    b.flipE = 0.0;
+    b.ebound = 0.0;
+    if (prec == kPrecI32) {
+        b.qscale = qscale;
+        b.init = Dq / qscale * 1.01;  // table units
+        b.unit = 0.0;
+        b.nupd_max = static_cast<int64_t>(4e18);
+        b.ebound = 0.5 * Ld * Dq * 1.01 + Ld * Ld * u64 * S;
+        return b;
+    }
+    const double uF = prec == kPrecF32 ? 0x1p-24 : u64;
+    const double Dc = prec == kPrecF32 ? D32 : 0.0;
+    b.init = (uF * S + Dc + (Ld + 4.0) * u64 * S) * 1.01 + 1e-15 * S;
     b.unit = uF * (1.001 * S + 2.0 * Jmax) * 1.01 + u64 * S;
     const double cap = 1e-3 * S / b.unit;
     b.nupd_max = cap > 4.0e18 ? static_cast<int64_t>(4e18) : static_cast<int64_t>(cap);
-    b.flipE = f32 ? (D32 + (static_cast<double>(L) + 512.0) * u64 * 1.001 * S) * 1.01 : 0.0;
+    if (prec == kPrecF32) {
+        b.flipE = (Ld + 512.0) * u64 * 1.001 * S * 1.01;
+        b.ebound = (0.5 * Ld * D32 + Ld * Ld * u64 * S) * 1.01;
+    }
     return b;
 }
 
@@ -87,10 +118,13 @@ struct Inst {
     double bound_init;         // bound on |h_table - h_exact| right after a refresh
     double bound_unit;         // added to that bound by each applied flip
     double bound_flipE;        // energy error per accepted flip of an FP32 table (0 otherwise)
+    double ebound;             // energy error right after a refresh (0: FP64 table)
+    double qscale;             // real value of one table unit (2^-k for I32, else 1)
     const double *J64;         // [L]
     const float *J32;          // [L]
+    const int32_t *Jq;         // [L] quantised couplings (I32 tables)
     uint8_t *spins;            // [R][L], states 0..q-1
-    void *h;                   // [R][q][L] field table backing store (float or double)
+    void *h;                   // [R][q][L] field table backing store (double, float or int32)
     double *E, *Eerr;          // [R] tracked energy and a rigorous bound on its error
     int64_t *nupd;             // [R] flips applied to the table since its last refresh
     int32_t *counts;           // [R][kQMax] number of sites per state
@@ -109,7 +143,7 @@ struct Inst {
 };
 
 struct Layout {
-    size_t J64, J32, spins, h, E, Eerr, nupd, counts, Mw, perm, slot_of, beta, acc6, fatt, facc,
+    size_t J64, J32, Jq, spins, h, E, Eerr, nupd, counts, Mw, perm, slot_of, beta, acc6, fatt, facc,
         xatt, xacc, serE, serM, events, ctr, bnd, T, phase, total;
 
     static size_t up(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
@@ -124,6 +158,7 @@ struct Layout {
         };
         J64 = take(sizeof(double) * L);
         J32 = take(sizeof(float) * L);
+        Jq = take(sizeof(int32_t) * L);
         spins = take(static_cast<size_t>(R) * L);
         h = take(fbytes * static_cast<size_t>(R) * q * L);
         E = take(sizeof(double) * R);

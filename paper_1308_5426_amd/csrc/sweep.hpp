@@ -21,6 +21,8 @@
 // sites and applies the flips in order, so no barrier is needed between
 // them).
 #pragma once
+#include <type_traits>
+
 #include "device_common.hpp"
 #include "state.hpp"
 
@@ -128,6 +130,14 @@ template <>
 __device__ __forceinline__ const float *coupling_src<float>(const Inst &P) { return P.J32; }
 template <>
 __device__ __forceinline__ const double *coupling_src<double>(const Inst &P) { return P.J64; }
+template <>
+__device__ __forceinline__ const int32_t *coupling_src<int32_t>(const Inst &P) { return P.Jq; }
+
+template <typename F>
+constexpr int table_prec()
+{
+    return sizeof(F) == sizeof(double) ? kPrecF64 : (__is_same(F, float) ? kPrecF32 : kPrecI32);
+}
 
 __device__ __forceinline__ void log_event(const Inst &P, int kind, int64_t a, int64_t b, int64_t c,
                                           int dec, double x)
@@ -212,10 +222,11 @@ __device__ __forceinline__ void store_walker(const Inst &P, const Walker<F> &W, 
 }
 
 // ---------------------------------------------------------------------------
-// Field table from the spins, FP64 accumulation.  For each state k a bitmask
-// per 64-site block lists the sites in state k; every thread owns sites j
-// and walks the set bits (wave-uniform, scalar), adding J*(|j - i|).  The
-// energy E = -1/2 sum_j h[s_j][j] is formed from the FP64 sums.
+// Field table from the spins, FP64 accumulation (exact for int tables).  For
+// each state k a bitmask per 64-site block lists the sites in state k; every
+// thread owns sites j and walks the set bits (wave-uniform, scalar), adding
+// the coupling to j.  The energy E = -1/2 sum_j h[s_j][j] (real units) is
+// formed from the FP64 sums.
 // ---------------------------------------------------------------------------
 template <typename F>
 __device__ __forceinline__ double refresh_fields(const Inst &P, Walker<F> &W)
@@ -257,7 +268,12 @@ __device__ __forceinline__ double refresh_fields(const Inst &P, Walker<F> &W)
                     m &= m - 1;
                     int d = jj - (blk * kWave + bit);
                     d += d < 0 ? L : 0;
-                    acc += W.J64[d];  // J*(0) = 0 removes the self term
+                    // J*(0) = 0 removes the self term.  FP32 / int tables sum their
+                    // own couplings (LDS), the FP64 table the FP64 ones.
+                    if constexpr (table_prec<F>() == kPrecF64)
+                        acc += W.J64[d];
+                    else
+                        acc += static_cast<double>(W.J[d]);
                 }
             }
             if (ok) {
@@ -266,7 +282,7 @@ __device__ __forceinline__ double refresh_fields(const Inst &P, Walker<F> &W)
             }
         }
     }
-    return -0.5 * block_sum(epart, W.red);
+    return -0.5 * block_sum(epart, W.red) * P.qscale;
 }
 
 // Exact energy of walker w from its spins in HBM: E = -1/2 sum_j sum_{i != j}
@@ -378,11 +394,16 @@ __device__ void exchange_step(const Inst &P, int64_t m, XScratch X, double *red)
         }
         __syncthreads();
     }
+    // FP32 / int tables keep tracking the energy of their own couplings (a
+    // constant bound off the exact one): exact energies served this step only
+    const bool keep = P.ebound > 0.0;
     for (int k = tid; k < R; k += NT) {
         P.perm[k] = X.perm[k];
         P.slot_of[X.perm[k]] = k;
-        P.E[k] = X.E[k];
-        P.Eerr[k] = X.Eerr[k];
+        if (!keep) {
+            P.E[k] = X.E[k];
+            P.Eerr[k] = X.Eerr[k];
+        }
     }
     __syncthreads();
 }
@@ -738,10 +759,11 @@ __device__ __forceinline__ double direct_dE_window(const Walker<F> &W, int L, in
 // error exactly as for two separately kept fields; a split pass adds `ex`
 // more such units per lane.
 template <typename F, bool D, bool DIR>
-__device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w, int64_t n, double beta, int t0,
+__device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w, int64_t n, double beta_r, int t0,
                                              int c0, int cend, ChainRegs &cr, int &pbuf)
 {
     constexpr bool kF64 = sizeof(F) == sizeof(double);
+    constexpr bool kI32 = table_prec<F>() == kPrecI32;
     const int L = P.L, q = P.q, lane = threadIdx.x & (kWave - 1);
     const bool lead = threadIdx.x < kWave;  // wave 0 keeps counters, events and energy increments
     uint32_t *sfirst = W.sfirst ? W.sfirst + (threadIdx.x / kWave) * L : nullptr;
@@ -767,6 +789,9 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
     double Bd = 2.0 * (P.bound_init + static_cast<double>(cr.nupd) * P.bound_unit);
     const double dBd = 2.0 * P.bound_unit;
     const double tfix = kBand + kEvalMargin;
+    // dE, its bounds and eL are in table units (real value = qscale * units; the
+    // scale is a power of two, 1 for FP tables), so beta is taken per unit
+    const double beta = beta_r * P.qscale;
     while (live) {
         ++cr.iters;
         const uint32_t pk = flip_word(i, a, b, lane);
@@ -813,10 +838,10 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
         if (lead && ((C >> lane) & 1ull)) {
             atomicAdd(&W.cnt[a], -1);
             atomicAdd(&W.cnt[b], 1);
-            if (kF64 || DIR) {  // FP32 tables take E from the flush's sums
-                cr.eL += dE;
-                cr.errL += Bdl;
-            }
+            // FP32 tables take E from the flush's sums; int tables' dE is exact
+            // in their quantised couplings (a constant bound covers the rest)
+            if (kF64 || DIR || kI32) cr.eL += dE;
+            if (kF64 || DIR) cr.errL += Bdl;
         }
         const int nc = __popcll(C);
         np += nc;
@@ -832,10 +857,12 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
             if (!accept && !((ballot(rej) >> m) & 1ull)) {
                 // |x| inside the trigger band: decide with the FP64 direct sum
                 const double d64 = chain_direct_dE(W, L, i_m, a_m, b_m);
-                const double x64 = beta * d64 + rl_d(lnu, m);
+                const double x64 = beta_r * d64 + rl_d(lnu, m);
                 accept = x64 < 0.0;
-                dEm = d64;
-                errm = 0.0;
+                if constexpr (!kI32) {  // int tables keep the energy of their own couplings
+                    dEm = d64;
+                    errm = 0.0;
+                }
                 if (lead && lane == 0) {
                     atomicAdd(&P.ctr[kCtrRecheck], 1ull);
                     if (fabs(x64) <= kBand) {
@@ -866,10 +893,8 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
                 if (lead && lane == m) {
                     atomicAdd(&W.cnt[a_m], -1);
                     atomicAdd(&W.cnt[b_m], 1);
-                    if (kF64 || DIR) {
-                        cr.eL += dEm;
-                        cr.errL += errm;
-                    }
+                    if (kF64 || DIR || kI32) cr.eL += dEm;
+                    if (kF64 || DIR) cr.errL += errm;
                 }
                 ++np;
                 if (!DIR) ++cr.nupd;
@@ -918,23 +943,25 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
 
 // Whole workgroup: apply the window's np flips to the table.  Each thread
 // owns M sites per pass and applies the flips to them in order, so no
-// barrier is needed between flips.  QT > 0 (q <= QT): the sites' fields of
-// the rows the window's flips touch sit in registers for the pass (one table
-// read and write per field; untouched rows are neither read nor written, which
-// matters when the table is in HBM) and every flip is applied to every row as
-// fma(coef, J, h) with a wave-uniform coefficient (-1, 0 or +1: from a table by
-// flip kind for QT = 4, computed from the flip's states for QT = 8), which
-// rounds exactly as h - J or h + J and leaves an untouched row's zeros alone;
-// QT = 0 (larger q): per batch of flips, the rows the batch touches are updated
-// one after another, each entry read and written once per batch, the next
-// row's read in flight during this row's update.  The couplings of kFlipBatch
-// flips are gathered before they are applied; with a doubled coupling row (D)
-// one address serves a flip's kFlushM gathers.  With an FP32 table the same
-// pass forms every flip's energy change in FP64 from the FP32 couplings it
-// already holds, sum_j J32(|j-i|)[delta(a, s_j) - delta(b, s_j)], over the spins
-// as they were just before it (partial sums per thread; the window-start spins
-// are recovered from the flip list, since the chain has already written the
-// new ones); its error against the exact change is at most the bound_flipE the
+// barrier is needed between flips.  QT > 0 (q <= QT, QT = 4, 6 or 8): the
+// sites' fields of the rows the window's flips touch sit in registers for the
+// pass (one table read and write per field; untouched rows are neither read
+// nor written, which matters when the table is in HBM) and every flip is
+// applied to all QT rows as fma(coef, J, h) with a wave-uniform coefficient (-1, 0 or +1:
+// from a table by flip kind for QT = 4, computed from the flip's states
+// otherwise), which rounds exactly as h - J or h + J and leaves an untouched
+// row's zeros alone; QT = 0 (larger q): per batch of flips, the rows the batch
+// touches are updated one after another, each entry read and written once per
+// batch, the next row's read in flight during this row's update.  Int tables
+// are updated in FP64 registers, exact for their integer values (|h| < 2^31):
+// the same fma form, no branch per flip.  The couplings of kFlipBatch flips are
+// gathered before they are applied; with a doubled coupling row (D) one address
+// serves a flip's kFlushM gathers.  With an FP32 table the same pass forms
+// every flip's energy change in FP64 from the FP32 couplings it already holds,
+// sum_j J32(|j-i|)[delta(a, s_j) - delta(b, s_j)], over the spins as they were
+// just before it (partial sums per thread; the window-start spins are
+// recovered from the flip list, since the chain has already written the new
+// ones); its error against the exact change is at most the bound_flipE the
 // caller charges per flip.
 template <typename F, int QT, bool D>
 __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np, double &part)
@@ -942,7 +969,9 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
     constexpr int QR = QT > 0 ? QT : 1;  // rows held in registers (q <= QT)
     constexpr int M = kFlushM;             // register slots per thread
     constexpr int B = kFlipBatch;
-    constexpr bool kF32 = sizeof(F) == sizeof(float);
+    constexpr bool kF32 = table_prec<F>() == kPrecF32;
+    constexpr bool kI32 = table_prec<F>() == kPrecI32;
+    using RT = typename std::conditional<kI32, double, F>::type;  // register arithmetic
     const int L = P.L, tid = threadIdx.x, NT = blockDim.x, lane = tid & (kWave - 1);
     static_assert(kMaxSweepThreads <= 256 && kMaxJobThreads <= 256, "M sites per thread assume <= 256 threads");
     const uint32_t pv = lane < np ? W.pend[lane] : kNoFlip;  // the chain already wrote the spins
@@ -957,7 +986,7 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
         const int j0 = jb + lane;
         int jm[M];
         bool ok[M];
-        F hr[QR][M];
+        RT hr[QR][M];
         int sr[M];
 #pragma unroll
         for (int m = 0; m < M; ++m) {
@@ -977,12 +1006,13 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
 #pragma unroll
         for (int c = 0; c < QT; ++c)
 #pragma unroll
-            for (int m = 0; m < M; ++m) hr[c][m] = (((touched >> c) & 1u) && ok[m]) ? W.h[c * L + jm[m]] : F(0);
+            for (int m = 0; m < M; ++m)
+                hr[c][m] = (((touched >> c) & 1u) && ok[m]) ? static_cast<RT>(W.h[c * L + jm[m]]) : RT(0);
         (void)hr;
         const F *Jrow = W.J + (j0 + L);  // D: coupling of site j0 + 64 m to site ip is Jrow[64 m - ip]
         for (int p0 = 0; p0 < np; p0 += B) {
             uint32_t pkb[B];
-            F g[B][M];
+            RT g[B][M];
 #pragma unroll
             for (int e = 0; e < B; ++e) {
                 // p0 + e <= 63; lanes past np hold the no-flip word
@@ -991,20 +1021,18 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
 #pragma unroll
                 for (int m = 0; m < M; ++m) {
                     if constexpr (D) {
-                        g[e][m] = Jrow[m * kWave - ip];
+                        g[e][m] = static_cast<RT>(Jrow[m * kWave - ip]);
                     } else {
                         int d = jm[m] - ip;
                         d += d < 0 ? L : 0;
-                        g[e][m] = W.J[d];
+                        g[e][m] = static_cast<RT>(W.J[d]);
                     }
                 }
             }
+            // no branch per flip: padding entries have all coefficients 0
+            if constexpr (QT == 4 && !kI32) {
 #pragma unroll
-            for (int e = 0; e < B; ++e) {
-                const bool real = p0 + e < np;
-                const int ip = fw_site(pkb[e]), ap = fw_old(pkb[e]), bp = fw_new(pkb[e]);
-                // no branch per flip: padding entries have all coefficients 0
-                if constexpr (QT == 4) {
+                for (int e = 0; e < B; ++e) {
                     const F *kc = W.ctab + ((pkb[e] >> 16) & 0x3Fu) * 4;  // one broadcast row per flip
 #pragma unroll
                     for (int c = 0; c < QT; ++c) {
@@ -1013,16 +1041,25 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
                         for (int m = 0; m < M; ++m)
                             hr[c][m] = fma(k, g[e][m], hr[c][m]);
                     }
-                } else if constexpr (QT > 0) {
+                }
+            } else if constexpr (QT > 0) {
+                // every row, flip by flip (no branch: QT * M independent fma per flip)
+#pragma unroll
+                for (int e = 0; e < B; ++e) {
+                    const int ap = fw_old(pkb[e]), bp = fw_new(pkb[e]);
 #pragma unroll
                     for (int c = 0; c < QT; ++c) {
-                        const F k = flip_coef<F>(c, ap, bp);  // wave-uniform; padding: 0
+                        const RT k = flip_coef<RT>(c, ap, bp);  // wave-uniform; padding: 0
 #pragma unroll
-                        for (int m = 0; m < M; ++m)
-                            hr[c][m] = fma(k, g[e][m], hr[c][m]);
+                        for (int m = 0; m < M; ++m) hr[c][m] = fma(k, g[e][m], hr[c][m]);
                     }
                 }
-                if (kF32) {
+            }
+            if (kF32) {
+#pragma unroll
+                for (int e = 0; e < B; ++e) {
+                    const bool real = p0 + e < np;
+                    const int ip = fw_site(pkb[e]), ap = fw_old(pkb[e]), bp = fw_new(pkb[e]);
 #pragma unroll
                     for (int m = 0; m < M; ++m) {
                         const int sj = sr[m];
@@ -1041,28 +1078,28 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
 #pragma unroll
                 for (int e = 0; e < B; ++e) rows |= (1u << fw_old(pkb[e])) | (1u << fw_new(pkb[e]));
                 int c = static_cast<int>(__builtin_ctz(rows));  // rows != 0: padding touches row 0
-                F vn[M];
+                RT vn[M];
 #pragma unroll
-                for (int m = 0; m < M; ++m) vn[m] = ok[m] ? W.h[c * L + jm[m]] : F(0);
+                for (int m = 0; m < M; ++m) vn[m] = ok[m] ? static_cast<RT>(W.h[c * L + jm[m]]) : RT(0);
                 while (c >= 0) {
-                    F v[M];
+                    RT v[M];
 #pragma unroll
                     for (int m = 0; m < M; ++m) v[m] = vn[m];
                     rows &= rows - 1u;
                     const int cn = rows ? static_cast<int>(__builtin_ctz(rows)) : -1;
                     if (cn >= 0) {
 #pragma unroll
-                        for (int m = 0; m < M; ++m) vn[m] = ok[m] ? W.h[cn * L + jm[m]] : F(0);
+                        for (int m = 0; m < M; ++m) vn[m] = ok[m] ? static_cast<RT>(W.h[cn * L + jm[m]]) : RT(0);
                     }
 #pragma unroll
                     for (int e = 0; e < B; ++e) {
-                        const F k = flip_coef<F>(c, fw_old(pkb[e]), fw_new(pkb[e]));  // padding: 0
+                        const RT k = flip_coef<RT>(c, fw_old(pkb[e]), fw_new(pkb[e]));  // padding: 0
 #pragma unroll
                         for (int m = 0; m < M; ++m) v[m] = fma(k, g[e][m], v[m]);
                     }
 #pragma unroll
                     for (int m = 0; m < M; ++m)
-                        if (ok[m]) W.h[c * L + jm[m]] = v[m];
+                        if (ok[m]) W.h[c * L + jm[m]] = static_cast<F>(v[m]);
                     c = cn;
                 }
             }
@@ -1071,7 +1108,7 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
         for (int c = 0; c < QT; ++c)
 #pragma unroll
             for (int m = 0; m < M; ++m)
-                if (((touched >> c) & 1u) && ok[m]) W.h[c * L + jm[m]] = hr[c][m];
+                if (((touched >> c) & 1u) && ok[m]) W.h[c * L + jm[m]] = static_cast<F>(hr[c][m]);
     }
 }
 
@@ -1153,36 +1190,57 @@ __device__ __forceinline__ double coupling_sum_wave(const double *J64, int L)
     return wave_sum(part);
 }
 
-// D32 = sum_r |J*(r) - J32(r)|, the FP32 couplings' total rounding, by one wave.
-__device__ __forceinline__ double coupling_f32_error_wave(const double *J64, const float *J32, int L)
+// sum_r |J*(r) - scale Jr(r)|, a coupling table's total rounding, by one wave.
+template <typename T>
+__device__ __forceinline__ double coupling_error_wave(const double *J64, const T *Jr, double scale, int L)
 {
     const int lane = threadIdx.x & (kWave - 1);
     double part = 0.0;
-    for (int r = 1 + lane; r < L; r += kWave) part += fabs(J64[r] - static_cast<double>(J32[r]));
+    for (int r = 1 + lane; r < L; r += kWave) part += fabs(J64[r] - scale * static_cast<double>(Jr[r]));
     return wave_sum(part) * 1.001;
 }
 
-// Table bounds of an instance from its couplings, by one whole wave; lane 0
-// stores them at P.bnd.
-__device__ __forceinline__ void store_bounds_wave(const Inst &P, bool f32)
+// After the couplings J64/J32 are written (the whole workgroup, at least one
+// wave): the quantised couplings Jq(r) = rint(J*(r) 2^k), k the largest with
+// S 2^k + L < 2^31 - 2 (no field of an int table can then overflow), and the
+// table bounds at P.bnd for precision prec (lane 0 of wave 0 writes them).
+__device__ void setup_couplings(const Inst &P, int prec)
 {
-    const double S = coupling_sum_wave(P.J64, P.L);
-    const double D32 = coupling_f32_error_wave(P.J64, P.J32, P.L);
-    if ((threadIdx.x & (kWave - 1)) == 0) *P.bnd = table_bounds(S, P.J64[1], D32, P.L, f32);
+    __shared__ double s_scale;
+    const int L = P.L;
+    double S = 0.0;
+    if (threadIdx.x < kWave) {
+        S = coupling_sum_wave(P.J64, L);
+        if (threadIdx.x == 0) {
+            int k = 0;
+            while (k < 60 && S * ldexp(1.0, k + 1) + static_cast<double>(L) < 2147483646.0) ++k;
+            s_scale = ldexp(1.0, k);
+        }
+    }
+    __syncthreads();
+    const double up = s_scale;
+    int32_t *Jq = const_cast<int32_t *>(P.Jq);
+    for (int r = threadIdx.x; r < L; r += blockDim.x) Jq[r] = static_cast<int32_t>(rint(P.J64[r] * up));
+    __syncthreads();
+    if (threadIdx.x < kWave) {
+        const double D32 = coupling_error_wave(P.J64, P.J32, 1.0, L);
+        const double Dq = coupling_error_wave(P.J64, P.Jq, 1.0 / up, L);
+        if (threadIdx.x == 0) *P.bnd = table_bounds(S, P.J64[1], D32, Dq, L, prec, 1.0 / up);
+    }
+    __syncthreads();
 }
 
-// Ladder and table bounds of a fresh instance (after k_jstar): beta_k = 1/T_k
-// from the temperatures at T (device memory), the identity slot permutation,
-// and the rigorous error bounds of the field table from S and J*(1), the
-// largest coupling.  One workgroup of at least one wave.
-__global__ void k_setup(Inst P, const double *__restrict__ T, int32_t f32)
+// Ladder, quantised couplings and table bounds of a fresh instance (after
+// k_jstar): beta_k = 1/T_k from the temperatures at T (device memory), the
+// identity slot permutation, and setup_couplings.  One workgroup.
+__global__ void k_setup(Inst P, const double *__restrict__ T, int32_t prec)
 {
     for (int k = threadIdx.x; k < P.R; k += blockDim.x) {
         const_cast<double *>(P.beta)[k] = 1.0 / T[k];
         P.perm[k] = k;
         P.slot_of[k] = k;
     }
-    if (threadIdx.x < kWave) store_bounds_wave(P, f32 != 0);
+    setup_couplings(P, prec);
 }
 
 // Current energy and magnetisation by temperature slot (E_slot[k] =
@@ -1208,7 +1266,7 @@ __global__ __launch_bounds__(kMaxSweepThreads) void k_refresh(Inst P, LdsPlan pl
     store_walker<F>(P, W, plan, w);
     if (threadIdx.x == 0) {
         P.E[w] = E;
-        P.Eerr[w] = 0.0;
+        P.Eerr[w] = P.ebound;
         P.nupd[w] = 0;
         int nmax = 0;
         for (int k = 0; k < P.q; ++k) nmax = max(nmax, W.cnt[k]);
@@ -1230,7 +1288,7 @@ __device__ __forceinline__ bool run_walker(const Inst &P, const LdsPlan &plan, u
     for (int k = 0; k < kPhN; ++k) ph.v[k] = 0;
     const uint64_t t_begin = ph.on ? clock64() : 0;
     constexpr bool TAB = PL != kPlDirect;
-    constexpr bool kF32Tab = TAB && sizeof(F) == sizeof(float);
+    constexpr bool kF32Tab = TAB && table_prec<F>() == kPrecF32;
     Walker<F> W = carve<F, PL, J64L>(lds, plan, P, w);
     load_walker<F>(P, W, plan, w);
     ChainRegs cr{P.E[w], P.Eerr[w], P.nupd[w], 0, 0.0, 0.0, 0u};
@@ -1246,8 +1304,8 @@ __device__ __forceinline__ bool run_walker(const Inst &P, const LdsPlan &plan, u
         // energy change of the sweep: the flush's sums over the FP32 couplings
         // (FP32 table) or the accepted flips' dE held by the chain lanes (FP64
         // table, or direct sums when there is no table)
-        cr.E += block_sum(part + cr.eL, W.red);
-        cr.Eerr += block_sum(cr.errL, W.red);
+        cr.E += block_sum(part + cr.eL, W.red) * P.qscale;
+        cr.Eerr += block_sum(cr.errL, W.red) * P.qscale;
         cr.eL = cr.errL = 0.0;
         if (tid == 0) {
             W.cs->nupd = cr.nupd;
@@ -1261,7 +1319,7 @@ __device__ __forceinline__ bool run_walker(const Inst &P, const LdsPlan &plan, u
         // without a table there is nothing to refresh (energies come from direct sums)
         if (TAB && ((P.refresh_every > 0 && (n + 1) % P.refresh_every == 0) || cr.nupd > P.nupd_max)) {
             cr.E = refresh_fields<F>(P, W);
-            cr.Eerr = 0.0;
+            cr.Eerr = P.ebound;
             cr.nupd = 0;
             if (tid == 0) atomicAdd(&P.ctr[kCtrRefresh], 1ull);
             __syncthreads();

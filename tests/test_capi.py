@@ -50,6 +50,20 @@ def test_host_only_calls():
     n32 = ctypes.c_size_t(0)
     assert lib.pt_workspace_size(1024, 3, 64, ctypes.byref(opt), ctypes.byref(n32)) == 0
     assert n32.value < n.value
+    opt.precision = pkg.PREC_I32
+    ni = ctypes.c_size_t(0)
+    assert lib.pt_workspace_size(1024, 3, 64, ctypes.byref(opt), ctypes.byref(ni)) == 0
+    assert ni.value == n32.value  # 4-byte table entries either way
+    opt.placement = pkg.PLACE_DIRECT  # direct sums keep no table: no int32 form
+    ctx = ctypes.c_void_p()
+    Tl = (ctypes.c_double * 2)(1.0, 2.0)
+    assert lib.pt_init(ctypes.byref(ctx), 10, 3, 0.5, ctypes.cast(Tl, ctypes.c_void_p), 2, 1,
+                       ctypes.byref(opt)) == pkg.PT_EINVAL
+    opt.placement = pkg.PLACE_AUTO
+    opt.precision = 3
+    assert lib.pt_init(ctypes.byref(ctx), 10, 3, 0.5, ctypes.cast(Tl, ctypes.c_void_p), 2, 1,
+                       ctypes.byref(opt)) == pkg.PT_EINVAL
+    opt.precision = pkg.PREC_F32
     assert lib.pt_workspace_size(1, 3, 64, ctypes.byref(opt), ctypes.byref(n)) == pkg.PT_EINVAL
     assert lib.pt_workspace_size(10, 17, 64, ctypes.byref(opt), ctypes.byref(n)) == pkg.PT_EINVAL
     assert b"bad sizes" in lib.pt_last_error()

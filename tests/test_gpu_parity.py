@@ -121,19 +121,25 @@ def test_small_config_trajectory_fp64(pkg, orc):
         np.testing.assert_allclose(obs[k], st[k], rtol=1e-12)
 
 
-def test_small_config_trajectory_fp32(pkg, orc):
-    """Same workload with the FP32 field table: decisions are FP64-exact through
-    the rechecks, so the trajectory is identical."""
+@pytest.mark.parametrize("precision", [1, 2])
+def test_small_config_trajectory_fp32_int32(pkg, orc, precision):
+    """Same workload with the FP32 field table and with the int32 table of
+    quantised couplings: decisions are FP64-exact through the rechecks, so the
+    trajectory is identical; energies within 1e-6 relative.  The FP32 table is
+    refreshed when its drift reaches the cap; the int32 table never drifts."""
     T = _ladder(0.3, 3.0, 16)
-    sim, ref = run_pair(pkg, orc, 64, 3, 0.5, T, 1234, 2000, 1, precision=1, steps=2)
+    sim, ref = run_pair(pkg, orc, 64, 3, 0.5, T, 1234, 2000, 1, precision=precision, steps=2)
     obs = sim.observables()
     E_ref = ref.energies()[ref.perm()]
     np.testing.assert_allclose(obs["E"], E_ref, rtol=1e-6)
-    print(f"[parity] C1 fp32: {obs['n_recheck']} rechecks, {obs['n_refresh']} refreshes", flush=True)
-    assert obs["n_refresh"] > 0  # the hot walkers' table drift reached its cap
+    print(f"[parity] C1 prec={precision}: {obs['n_recheck']} rechecks, {obs['n_refresh']} refreshes", flush=True)
+    if precision == 1:
+        assert obs["n_refresh"] > 0  # the hot walkers' table drift reached its cap
+    else:
+        assert obs["n_refresh"] == 0
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_fused_equals_unfused(pkg, orc, precision):
     """Persistent launch with device-side exchange vs one launch per sweep and
     per exchange step."""
@@ -148,6 +154,15 @@ def test_fused_equals_unfused(pkg, orc, precision):
 def test_tiles_and_ragged_sizes(pkg, orc, L, q, threads):
     T = _ladder(0.2, 3.0, 6)
     run_pair(pkg, orc, L, q, 0.45, T, 99, 20, 1, threads=threads, steps=2, mode=1 if L >= 1000 else 0)
+
+
+@pytest.mark.parametrize("L,q,threads", [(100, 2, 64), (1000, 5, 256), (257, 16, 128), (2, 2, 64), (1000, 7, 192),
+                                         (2500, 3, 256)])
+def test_tiles_and_ragged_sizes_int32(pkg, orc, L, q, threads):
+    """The int32 table across tile shapes, ragged sizes and the three flush
+    forms (four rows, eight rows, row by row)."""
+    T = _ladder(0.2, 3.0, 6)
+    run_pair(pkg, orc, L, q, 0.45, T, 99, 20, 1, precision=2, threads=threads, steps=2, mode=1 if L >= 1000 else 0)
 
 
 def test_single_replica(pkg, orc):
@@ -170,7 +185,7 @@ def test_medium_config_sampled(pkg, orc):
     drift-driven refreshes, with near-threshold FP64 rechecks), FP64 table for
     12 sweeps."""
     T = _ladder(0.3, 3.0, 64)
-    for prec, nsw in ((1, 40), (0, 12)):
+    for prec, nsw in ((1, 40), (2, 40), (0, 12)):
         sim, ref = run_pair(pkg, orc, 1024, 3, 0.4, T, 1234, nsw, 1, precision=prec, mode=1, steps=2)
         obs = sim.observables()
         E_ref = ref.energies()[ref.perm()]
@@ -178,10 +193,12 @@ def test_medium_config_sampled(pkg, orc):
         st = ref.stats()
         np.testing.assert_array_equal(obs["flip_acc"], st["flip_acc"])
         np.testing.assert_array_equal(obs["xchg_acc"], st["xchg_acc"])
-        if prec:
-            print(f"[parity] C2 fp32: {obs['n_recheck']} rechecks, {obs['n_refresh']} refreshes", flush=True)
+        print(f"[parity] C2 prec={prec}: {obs['n_recheck']} rechecks, {obs['n_refresh']} refreshes", flush=True)
+        if prec == 1:
             assert obs["n_recheck"] > 0
             assert obs["n_refresh"] > 0
+        if prec == 2:
+            assert obs["n_refresh"] == 0
 
 
 def test_checkpoint_resume(pkg, orc):
@@ -210,19 +227,20 @@ def test_invalid_arguments(pkg):
         assert ei.value.status == pkg.PT_EINVAL
 
 
-@pytest.mark.parametrize("placement", [0, 2, 3])
-def test_large_config_all_walkers(pkg, orc, placement):
+@pytest.mark.parametrize("placement,precision", [(0, 1), (2, 1), (3, 1), (0, 2), (2, 0)])
+def test_large_config_all_walkers(pkg, orc, placement, precision):
     """L = 16384, q = 5, sigma = 0.3, 128 replicas geometric in [0.2, 2.5], ordered
     start, FP32 form, at the real launch shape: three sweeps of every walker with
     the fused exchange step after each, against the oracle on all walkers, with
     the field table in HBM (the automatic choice: it does not fit in LDS) and
-    with direct sums and no table."""
+    with direct sums and no table; also the int32 and FP64 tables in HBM."""
     from workloads import large
 
     inst = large()
     nsw = 3
-    print(f"[parity] large L={inst.L} q={inst.q} R={inst.R} placement={placement} sweeps={nsw}", flush=True)
-    sim = pkg.Simulation(inst.L, inst.q, inst.sigma, inst.T, inst.seed, precision=1, init=inst.init,
+    print(f"[parity] large L={inst.L} q={inst.q} R={inst.R} placement={placement} precision={precision} "
+          f"sweeps={nsw}", flush=True)
+    sim = pkg.Simulation(inst.L, inst.q, inst.sigma, inst.T, inst.seed, precision=precision, init=inst.init,
                          placement=placement)
     assert sim.plan()["placement"] == (placement or pkg.PLACE_HBM)
     sim.run(nsw, 1)
@@ -241,5 +259,5 @@ def test_large_config_all_walkers(pkg, orc, placement):
     # direct sums: the oracle's initial energy is a sequential sum of L(L-1)/2
     # terms, whose rounding error is bounded by (L^2/2) 2^-53 |E| (about 1.5e-8
     # here); FP32 table: energy changes summed from the FP32 couplings, 1e-6
-    rtol = inst.L * inst.L / 2 * 2.0**-53 if placement == 3 else 1e-6
+    rtol = inst.L * inst.L / 2 * 2.0**-53 if (placement == 3 or precision == 0) else 1e-6
     np.testing.assert_allclose(obs["E"], ref.energies()[ref.perm()], rtol=rtol)

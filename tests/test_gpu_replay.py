@@ -29,7 +29,7 @@ def _replay(ref, events):
                    ex=[(a, b, c, d) for (k, a, b, c, d, _) in events if k == 1])
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_metropolis_band_logged_and_replayed(pkg, orc, precision):
     L, q, sigma = 24, 3, 0.5
     seed, T, _ = metropolis_case(orc, L, q, sigma)
@@ -51,7 +51,7 @@ def test_metropolis_band_logged_and_replayed(pkg, orc, precision):
     np.testing.assert_allclose(obs["E"], ref.energies()[ref.perm()], rtol=1e-6 if precision else 1e-12)
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_exchange_band_logged_and_replayed(pkg, orc, precision):
     L, q, sigma = 24, 3, 0.5
     seed, T = exchange_case(orc, L, q, sigma)
