@@ -64,7 +64,10 @@ def kernel_source_sha():
 def algorithmic_bytes(obs, inst, prec, placement):
     """Bytes the method must move per launch, by placement of the field table.
 
-    Table in LDS (f = 4 B FP32 / 8 B FP64 per entry): per attempt the spin s_i
+    Table in HBM (f bytes per entry; the bound is HBM): per attempt two table
+    entries (2 f), per accepted flip two table rows read and written (4 f L), per
+    refresh the table written (f q L).
+    Table in LDS (f = 4 B FP32 / int32, 8 B FP64 per entry): per attempt the spin s_i
     and two table entries (1 + 2 f); per accepted flip one coupling row read
     and two table rows read and written (5 f L); per refresh one FP64 coupling
     per site pair (8 L^2); per recheck one FP64 coupling and one spin per site
@@ -77,6 +80,8 @@ def algorithmic_bytes(obs, inst, prec, placement):
     common = inst.R * inst.sweeps * 5 * inst.L + obs["exchange_steps"] * 8 * inst.R
     if placement == 3:
         return attempts * 9 * inst.L + common, acc
+    if placement == 2:  # the table's side in HBM: two entries per attempt, two rows read and written per flip
+        return attempts * 2 * fb + acc * 4 * fb * inst.L + obs["n_refresh"] * fb * inst.q * inst.L, acc
     return (attempts * (1 + 2 * fb) + acc * 5 * fb * inst.L + obs["n_refresh"] * 8 * inst.L * inst.L
             + obs["n_recheck"] * 9 * inst.L + common), acc
 
@@ -342,21 +347,26 @@ def lds_peak_measured():
     return bw.value
 
 
-def load_traffic(sha, name):
-    """HBM bytes per launch of the sweep kernel from a committed counter
-    summary (lines `key: value`), if it was taken on these kernel sources."""
-    p = os.path.join(ROOT, "profiles", name)
-    if not os.path.exists(p):
-        return None
-    d = {}
-    with open(p) as f:
-        for line in f:
-            if ":" in line and not line.startswith(("#", "`", " ", "|")):
-                k, v = line.split(":", 1)
-                d[k.strip()] = v.strip()
-    if d.get("source_sha") != sha or "hbm_bytes_per_launch" not in d:
-        return None
-    return {"hbm_bytes_per_launch": float(d["hbm_bytes_per_launch"])}
+def load_traffic(sha, key):
+    """Counter figures of the sweep kernel from the committed summaries in
+    profiles/ (lines `key: value`) whose workload key and kernel-source hash
+    match: LDS bytes per launch (SQ_INSTS_LDS_*_BANDWIDTH x 64 B) and HBM bytes
+    per launch (FETCH_SIZE and WRITE_SIZE, calibrated by a copy kernel)."""
+    out = {}
+    d = os.path.join(ROOT, "profiles")
+    for name in sorted(os.listdir(d)):
+        vals = {}
+        with open(os.path.join(d, name)) as f:
+            for line in f:
+                if ":" in line and not line.startswith(("#", "`", " ", "|")):
+                    k, v = line.split(":", 1)
+                    vals[k.strip()] = v.strip()
+        if vals.get("key") != key or vals.get("source_sha") != sha:
+            continue
+        for k in ("lds_bytes_per_launch", "hbm_bytes_per_launch"):
+            if k in vals:
+                out[k] = float(vals[k])
+    return out
 
 
 def main():
@@ -421,11 +431,11 @@ def main():
     bytes_, acc = algorithmic_bytes(obs, inst, prec, plan["placement"])
     achieved = bytes_ / kern
     sha = kernel_source_sha()
-    tr = load_traffic(sha, f"pmc_k_sweep_{args.workload}_{args.precision}.md")
-    traffic = None if tr is None else tr["hbm_bytes_per_launch"]
+    tr = load_traffic(sha, f"{args.workload}_{args.precision}_{PLACE_NAMES[plan['placement']]}")
     occupied = min(CUS, inst.R)
     lds_meas = lds_peak_measured()
-    peak = LDS_PEAK
+    hbm_bound = plan["placement"] == 2
+    peak = HBM_PEAK if hbm_bound else LDS_PEAK
     out = {
         "metric": "spin-flip attempts/sec (all replicas)",
         "value": value,
@@ -448,19 +458,24 @@ def main():
             "threads_per_walker": plan["threads"], "lds_bytes_per_walker": plan["lds_bytes"],
         },
         "roofline": {
-            "bound": "lds",
+            "bound": "hbm" if hbm_bound else "lds",
             "kernel": "k_sweep (persistent, exchange fused)",
             "achieved": achieved / 1e9,
             "peak": peak / 1e9,
             "unit": "GB/s",
             "frac": achieved / peak,
             "frac_occupied_cus": achieved / (peak * occupied / CUS),
-            "peak_note": "256 B/clk/CU x 256 CUs x 2.4 GHz (CDNA 4 LDS read bandwidth); the probe's measured "
+            "peak_note": "8 TB/s HBM3E" if hbm_bound else
+                         "256 B/clk/CU x 256 CUs x 2.4 GHz (CDNA 4 LDS read bandwidth); the probe's measured "
                          "rate is an achievable reference, not the peak",
             "probe_measured": None if lds_meas is None else lds_meas / 1e9,
-            "traffic": traffic,
-            "traffic_note": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated by a copy kernel) from "
-                            "the committed counter summary of these kernel sources, else null",
+            "traffic": tr.get("lds_bytes_per_launch"),
+            "traffic_note": "LDS bytes per launch measured by SQ_INSTS_LDS_LOAD/STORE/ATOMIC_BANDWIDTH (64 B units, "
+                            "exact on the LDS probe) in the committed counter summary of these kernel sources, "
+                            "else null",
+            "hbm_traffic": tr.get("hbm_bytes_per_launch"),
+            "hbm_traffic_note": "HBM bytes per launch: FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for "
+                                "a 1 GiB device copy, from the committed summary of these kernel sources, else null",
             "kernel_ms": kern * 1e3,
             "algorithmic_bytes_per_launch": bytes_,
             "accepted_flips_per_launch": acc,
@@ -477,7 +492,7 @@ def main():
         ph = one_step(False, profile=True)
         out["phases"] = phase_summary(ph, inst, prec, plan["placement"])
     if not prec and inst.q <= 4 and inst.L <= 3000:
-        out["field_update_alone"] = field_update_alone(inst, peak)
+        out["field_update_alone"] = field_update_alone(inst, LDS_PEAK)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds, mode=0)
     if args.workload == "medium" and not args.no_batch:

@@ -1,25 +1,34 @@
-"""Build the gfx950 HIP library libptmi.so in-tree with hipcc."""
+"""Build the gfx950 HIP library libptmi.so in-tree with hipcc.
+
+The library is compiled from several sources in parallel (the host runtime and
+C ABI in csrc/ptmi.hip, the kernel variants of each field-table precision in
+csrc/kernels_<prec>.hip) and linked into one shared object; the LDS bandwidth
+probe is a library of its own."""
 from __future__ import annotations
 
 import os
 import shutil
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "ptmi.hip")
+CSRC = os.path.join(HERE, "csrc")
+SOURCES = ["ptmi.hip", "kernels_f64.hip", "kernels_f32.hip", "kernels_i32.hip"]
 LIB = os.path.join(HERE, "libptmi.so")
-PROBE_SRC = os.path.join(HERE, "csrc", "lds_probe.hip")
+PROBE_SRC = os.path.join(CSRC, "lds_probe.hip")
 PROBE_LIB = os.path.join(HERE, "libptmi_probe.so")
+OBJ_DIR = os.path.join(HERE, "_build")
 ARCH = os.environ.get("PTMI_ARCH", "gfx950")
 
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared",
+    "-O3", "-std=c++17", "-fPIC",
     f"--offload-arch={ARCH}",
     # packed FP32 instructions are disabled for all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]
+INCLUDES = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
 def hipcc() -> str:
@@ -29,23 +38,39 @@ def hipcc() -> str:
     return exe
 
 
-def _compile(src, lib, verbose):
-    tmp = lib + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"), src, "-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd, cwd=HERE)
+
+
+def _object(src, verbose):
+    obj = os.path.join(OBJ_DIR, os.path.splitext(src)[0] + ".o")
+    _run([hipcc(), *FLAGS, *INCLUDES, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
+    return obj
+
+
+def _link(objs, lib, verbose):
+    tmp = lib + ".tmp%d" % os.getpid()
+    _run([hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp], verbose)
     os.replace(tmp, lib)
 
 
-def build(verbose: bool = False) -> str:
-    """Compile csrc/ptmi.hip (and the headers it includes) into libptmi.so, and
-    the LDS bandwidth probe into libptmi_probe.so."""
-    from concurrent.futures import ThreadPoolExecutor
+def _probe(verbose):
+    tmp = PROBE_LIB + ".tmp%d" % os.getpid()
+    _run([hipcc(), *FLAGS, "-shared", *INCLUDES, PROBE_SRC, "-o", tmp], verbose)
+    os.replace(tmp, PROBE_LIB)
 
-    with ThreadPoolExecutor(2) as ex:
-        for f in [ex.submit(_compile, SRC, LIB, verbose), ex.submit(_compile, PROBE_SRC, PROBE_LIB, verbose)]:
-            f.result()
+
+def build(verbose: bool = False) -> str:
+    """Compile csrc/ptmi.hip and csrc/kernels_*.hip (with the headers they
+    include) into libptmi.so, and the LDS bandwidth probe into libptmi_probe.so."""
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    with ThreadPoolExecutor(len(SOURCES) + 1) as ex:
+        probe = ex.submit(_probe, verbose)
+        objs = [f.result() for f in [ex.submit(_object, s, verbose) for s in SOURCES]]
+        _link(objs, LIB, verbose)
+        probe.result()
     return LIB
 
 

@@ -122,7 +122,7 @@ __device__ __forceinline__ void jstar_entry(int32_t L, double sigma, int r, doub
 // Zero fill of device memory (used instead of a memset node, so the call can
 // also be captured in a graph): 8-byte words when pointer and size allow,
 // bytes otherwise.
-__global__ void k_zero(unsigned char *__restrict__ p, size_t n)
+static __global__ void k_zero(unsigned char *__restrict__ p, size_t n)
 {
     const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
     const size_t t0 = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -134,7 +134,7 @@ __global__ void k_zero(unsigned char *__restrict__ p, size_t n)
     }
 }
 
-__global__ void k_jstar(int32_t L, double sigma, double *__restrict__ J64, float *__restrict__ J32)
+static __global__ void k_jstar(int32_t L, double sigma, double *__restrict__ J64, float *__restrict__ J32)
 {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r <= L / 2) jstar_entry(L, sigma, r, J64, J32);

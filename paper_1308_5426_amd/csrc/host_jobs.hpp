@@ -48,14 +48,11 @@ pt_status job_plan(const pt_job_desc &j, int prec, int budget, int threads, LdsP
     return PT_OK;
 }
 
-template <typename F>
-const void *jobs_fn() { return reinterpret_cast<const void *>(&k_jobs<F>); }
-
 const void *jobs_fn_prec(int prec)
 {
-    if (prec == PT_PREC_F32) return jobs_fn<float>();
-    if (prec == PT_PREC_I32) return jobs_fn<int32_t>();
-    return jobs_fn<double>();
+    if (prec == PT_PREC_F32) return jobs_kernel_f32();
+    if (prec == PT_PREC_I32) return jobs_kernel_i32();
+    return jobs_kernel_f64();
 }
 
 // Resident workgroups of k_jobs for (threads, budget) on this device.

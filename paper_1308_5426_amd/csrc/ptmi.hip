@@ -14,7 +14,7 @@
 #include <vector>
 
 #include "ptmi.h"
-#include "jobs.hpp"
+#include "kernels.hpp"
 
 using namespace ptmi;
 
@@ -175,67 +175,19 @@ pt_status validate(int32_t L, int32_t q, double sigma, const double *T, int32_t 
     return PT_OK;
 }
 
-// Kernel variant by the number of states (four, six or eight flush rows in
-// registers for q <= 4, 6 or 8; row by row beyond), by where the field table
-// lives and by whether the FP64 couplings are in LDS.
-template <typename F, int PL, bool J64L>
-const void *sweep_fn_q(int q)
-{
-    if constexpr (PL == kPlDirect) return reinterpret_cast<const void *>(&k_sweep<F, 0, PL, J64L>);
-    if (q <= 4) return reinterpret_cast<const void *>(&k_sweep<F, 4, PL, J64L>);
-    if (q <= 6) return reinterpret_cast<const void *>(&k_sweep<F, 6, PL, J64L>);
-    if (q <= 8) return reinterpret_cast<const void *>(&k_sweep<F, 8, PL, J64L>);
-    return reinterpret_cast<const void *>(&k_sweep<F, 0, PL, J64L>);
-}
-template <typename F, int PL>
-const void *sweep_fn_j(int q, const LdsPlan &p)
-{
-    if constexpr (table_prec<F>() == kPrecF64)  // FP64 couplings are the table's own, always in LDS
-        return sweep_fn_q<F, PL, true>(q);
-    else if constexpr (table_prec<F>() == kPrecI32)  // never in LDS
-        return sweep_fn_q<F, PL, false>(q);
-    else
-        return p.j64_in_lds ? sweep_fn_q<F, PL, true>(q) : sweep_fn_q<F, PL, false>(q);
-}
-template <typename F>
-const void *sweep_fn(int q, const LdsPlan &p)
-{
-    switch (p.place) {
-    case kPlLds: return sweep_fn_j<F, kPlLds>(q, p);
-    case kPlHbm: return sweep_fn_j<F, kPlHbm>(q, p);
-    default:
-        if constexpr (table_prec<F>() == kPrecI32) return nullptr;  // no table: not an int form
-        else return sweep_fn_j<F, kPlDirect>(q, p);
-    }
-}
-template <typename F, int PL>
-const void *refresh_fn_j(const LdsPlan &p)
-{
-    if constexpr (table_prec<F>() == kPrecF64) return reinterpret_cast<const void *>(&k_refresh<F, PL, true>);
-    else if constexpr (table_prec<F>() == kPrecI32) return reinterpret_cast<const void *>(&k_refresh<F, PL, false>);
-    else
-        return p.j64_in_lds ? reinterpret_cast<const void *>(&k_refresh<F, PL, true>)
-                            : reinterpret_cast<const void *>(&k_refresh<F, PL, false>);
-}
-template <typename F>
-const void *refresh_fn(const LdsPlan &p)
-{
-    // refreshes of an HBM table and of a direct-sum walker (whose HBM table is
-    // never read) run the same code
-    return p.place == kPlLds ? refresh_fn_j<F, kPlLds>(p) : refresh_fn_j<F, kPlHbm>(p);
-}
-
+// Kernels by table precision (each precision's kernels are built in a source
+// file of their own, kernels_<prec>.hip).
 const void *sweep_fn_prec(int prec, int q, const LdsPlan &p)
 {
-    if (prec == PT_PREC_F32) return sweep_fn<float>(q, p);
-    if (prec == PT_PREC_I32) return sweep_fn<int32_t>(q, p);
-    return sweep_fn<double>(q, p);
+    if (prec == PT_PREC_F32) return sweep_kernel_f32(q, p);
+    if (prec == PT_PREC_I32) return sweep_kernel_i32(q, p);
+    return sweep_kernel_f64(q, p);
 }
 const void *refresh_fn_prec(int prec, const LdsPlan &p)
 {
-    if (prec == PT_PREC_F32) return refresh_fn<float>(p);
-    if (prec == PT_PREC_I32) return refresh_fn<int32_t>(p);
-    return refresh_fn<double>(p);
+    if (prec == PT_PREC_F32) return refresh_kernel_f32(p);
+    if (prec == PT_PREC_I32) return refresh_kernel_i32(p);
+    return refresh_kernel_f64(p);
 }
 
 pt_status set_lds_attr(const void *fn, int bytes)

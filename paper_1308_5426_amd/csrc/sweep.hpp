@@ -160,7 +160,7 @@ __device__ __forceinline__ uint8_t initial_spin(const Inst &P, int w, int j, boo
     return static_cast<uint8_t>(__umulhi(o.x, static_cast<uint32_t>(P.q)));
 }
 
-__global__ void k_init_spins(Inst P, int32_t ordered)
+static __global__ void k_init_spins(Inst P, int32_t ordered)
 {
     const int64_t total = static_cast<int64_t>(P.R) * P.L;
     for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total;
@@ -1233,7 +1233,7 @@ __device__ void setup_couplings(const Inst &P, int prec)
 // Ladder, quantised couplings and table bounds of a fresh instance (after
 // k_jstar): beta_k = 1/T_k from the temperatures at T (device memory), the
 // identity slot permutation, and setup_couplings.  One workgroup.
-__global__ void k_setup(Inst P, const double *__restrict__ T, int32_t prec)
+static __global__ void k_setup(Inst P, const double *__restrict__ T, int32_t prec)
 {
     for (int k = threadIdx.x; k < P.R; k += blockDim.x) {
         const_cast<double *>(P.beta)[k] = 1.0 / T[k];
@@ -1245,7 +1245,7 @@ __global__ void k_setup(Inst P, const double *__restrict__ T, int32_t prec)
 
 // Current energy and magnetisation by temperature slot (E_slot[k] =
 // E[perm[k]]), for a caller that copies observables without host staging.
-__global__ void k_obs_by_slot(Inst P, double *__restrict__ Eslot, double *__restrict__ Mslot)
+static __global__ void k_obs_by_slot(Inst P, double *__restrict__ Eslot, double *__restrict__ Mslot)
 {
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < P.R; k += gridDim.x * blockDim.x) {
         const int w = P.perm[k];
@@ -1369,7 +1369,7 @@ __global__ __launch_bounds__(kMaxSweepThreads) void k_sweep(Inst P, LdsPlan plan
     (void)run_walker<F, QT, PL, J64L>(P, plan, lds, blockIdx.x, n0, nsw, xevery, x0, m0, fused != 0);
 }
 
-__global__ __launch_bounds__(1024) void k_exchange(Inst P, int64_t m)
+static __global__ __launch_bounds__(1024) void k_exchange(Inst P, int64_t m)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     double *red = reinterpret_cast<double *>(lds);
