@@ -117,7 +117,7 @@ def phase_summary(ph, inst, prec, placement):
     return out
 
 
-def run_gpu(inst, prec, steps, warmup, max_chunk=0, placement=0):
+def run_gpu(inst, prec, steps, warmup, max_chunk=0, placement=0, threads=0):
     import torch
 
     import paper_1308_5426_amd as pkg
@@ -131,7 +131,8 @@ def run_gpu(inst, prec, steps, warmup, max_chunk=0, placement=0):
     def one_step(timed, profile=False):
         nonlocal obs_last, plan
         sim = pkg.Simulation(inst.L, inst.q, inst.sigma, inst.T, inst.seed, precision=prec, init=inst.init,
-                             max_sweeps_per_launch=max_chunk or inst.sweeps, placement=placement, profile=profile)
+                             max_sweeps_per_launch=max_chunk or inst.sweeps, placement=placement, profile=profile,
+                             threads=threads)
         plan = sim.plan()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -424,7 +425,8 @@ def main():
     placement = {"auto": 0, "lds": 1, "hbm": 2, "direct": 3}[args.placement]
     # the L = 16384 instance runs in launches of 250 sweeps (progress between them)
     elapsed, tk, obs, plan, one_step = run_gpu(inst, prec, args.steps, args.warmup,
-                                               max_chunk=250 if inst.L > 8192 else 0, placement=placement)
+                                               max_chunk=250 if inst.L > 8192 else 0, placement=placement,
+                                               threads=args.threads)
     attempts = inst.L * inst.R * inst.sweeps
     value = attempts * args.steps / elapsed
     kern = sum(tk) / len(tk)

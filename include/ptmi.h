@@ -81,7 +81,10 @@ typedef struct {
     int32_t placement;      /* PT_PLACE_*: where the field table lives during a sweep (AUTO:
                                LDS when it fits, else HBM; DIRECT: no table, direct sums) */
     int32_t threads;        /* threads per walker workgroup (multiple of 64, <= 256); 0 = auto
-                               (single instance: 64 per 256 sites, at most 256; batch/server: 256) */
+                               (single instance: 64 per 256 sites, at most 256; batch/server: 256);
+                               512 (single instance, FP64 or int32 table in LDS, q <= 4,
+                               256 <= L <= 1024): the overlapped sweep, the chain of each window
+                               beside the previous window's flush in separate waves */
     int32_t refresh_every;  /* sweeps between O(L^2) recomputations of the fields; 0 = auto */
     int32_t series_capacity;/* sweeps of per-slot E and M to keep (0 = none) */
     int32_t event_capacity; /* entries of the banded-event log (0 = 4096) */
@@ -290,6 +293,9 @@ pt_status pt_batch_free(pt_batch *b);
 /* ------------------------------------------------------------------------ */
 typedef struct pt_server pt_server;
 
+/* Device bytes a server needs for an arena of arena_bytes and max_jobs
+ * submissions: the size of a caller workspace (opt->workspace) for it. */
+pt_status pt_server_workspace_size(size_t arena_bytes, int32_t max_jobs, size_t *bytes);
 /* arena_bytes of device memory for job state (opt->workspace may supply it);
  * max_jobs bounds the number of submissions over the server's life.  The
  * server's kernel stays resident until pt_server_stop: a device-wide

@@ -85,7 +85,7 @@ EXPORTS = [
     "pt_get_plan", "pt_get_phase_counters", "pt_reset_stats", "pt_synchronize", "pt_save", "pt_load", "pt_free", "pt_last_error",
     "pt_batch_workspace_size", "pt_batch_create", "pt_batch_run", "pt_batch_observables",
     "pt_batch_get_spins", "pt_batch_shape", "pt_batch_free",
-    "pt_server_start", "pt_server_submit", "pt_server_poll", "pt_server_wait", "pt_server_times",
+    "pt_server_workspace_size", "pt_server_start", "pt_server_submit", "pt_server_poll", "pt_server_wait", "pt_server_times",
     "pt_server_get_spins", "pt_server_stop", "pt_run_static",
 ]
 STATIC_SCRATCH_BYTES = 64 << 20
@@ -137,6 +137,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.pt_batch_get_spins.argtypes = [_P, i32, _P, _P]
     L.pt_batch_shape.argtypes = [_P, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.pt_batch_free.argtypes = [_P]
+    L.pt_server_workspace_size.argtypes = [ctypes.c_size_t, i32, ctypes.POINTER(ctypes.c_size_t)]
     L.pt_server_start.argtypes = [pp, ctypes.c_size_t, i32, OP]
     L.pt_server_submit.argtypes = [_P, JD, ctypes.POINTER(i64)]
     L.pt_server_poll.argtypes = [_P, i64, ctypes.POINTER(i32), OB]
@@ -454,6 +455,11 @@ class Server:
         opt = Options()
         self._lib.pt_default_options(ctypes.byref(opt))
         opt.precision, opt.threads, opt.lds_budget = int(precision), int(threads), int(lds_budget)
+        # the device arena and control words come from PyTorch
+        nbytes = ctypes.c_size_t(0)
+        _check(self._lib.pt_server_workspace_size(int(arena_bytes), int(max_jobs), ctypes.byref(nbytes)))
+        self._ws, _ = _torch_device_memory(nbytes.value)
+        opt.workspace, opt.workspace_bytes = self._ws.data_ptr(), self._ws.numel()
         h = ctypes.c_void_p()
         _check(self._lib.pt_server_start(ctypes.byref(h), int(arena_bytes), int(max_jobs), ctypes.byref(opt)))
         self._h = h
@@ -495,6 +501,7 @@ class Server:
         if getattr(self, "_h", None):
             h, self._h = self._h, None
             _check(self._lib.pt_server_stop(h))
+            self._ws = None  # the launch has ended: the arena goes back to PyTorch
 
     def __del__(self):
         try:

@@ -31,18 +31,31 @@ pt_status validate_job(const pt_job_desc &j)
     return PT_OK;
 }
 
+// Device bytes of a server: the job arena, the ticket counter, and one pair of
+// ready / finished words per job slot.
+size_t server_bytes(size_t arena_bytes, int32_t max_jobs)
+{
+    return Layout::up(arena_bytes) + Layout::up(sizeof(JobControl)) +
+           Layout::up(sizeof(unsigned long long) * 2 * static_cast<size_t>(max_jobs));
+}
+
 size_t job_bytes(const pt_job_desc &j, int prec)
 {
     return Layout::up(layout_of(j.L, j.q, j.R, prec, 0, kJobEvents).total);
 }
 
-// Carve of one job inside a workgroup LDS budget: table in LDS if it fits,
-// else in HBM; which kernel variant runs it.
+// Carve of one job inside a workgroup LDS budget, and which kernel variant
+// runs it: the table in LDS if it fits; else, for q <= 6, in HBM (four or six
+// register rows per flush: 1.7x faster than direct sums on the 16384-site,
+// q = 5 instance), and for larger q direct sums with no table (the HBM flush
+// then updates eight rows, or row by row, per flip: the 256-job batch ran at
+// half the speed of direct sums); int32 tables always keep their table.
 pt_status job_plan(const pt_job_desc &j, int prec, int budget, int threads, LdsPlan *plan, int32_t *variant)
 {
     const size_t b = static_cast<size_t>(budget);
     const bool in_lds = make_plan(j.L, j.q, j.R, prec, true, kPlLds, b, threads, plan);
-    if (!in_lds && !make_plan(j.L, j.q, j.R, prec, true, kPlHbm, b, threads, plan))
+    const int spill = (j.q <= 6 || prec == PT_PREC_I32) ? kPlHbm : kPlDirect;
+    if (!in_lds && !make_plan(j.L, j.q, j.R, prec, true, spill, b, threads, plan))
         return fail(PT_EINVAL, "job with L = %d, R = %d does not fit an LDS budget of %d B", j.L, j.R, budget);
     *variant = job_variant(plan->place, j.q, plan->j64_in_lds != 0);
     return PT_OK;
@@ -505,7 +518,7 @@ pt_status pt_server_start(pt_server **out, size_t arena_bytes, int32_t max_jobs,
     s->arena_bytes = Layout::up(arena_bytes);
     s->ctl_off = s->arena_bytes;
     s->jc_off = s->ctl_off + Layout::up(sizeof(JobControl));
-    const size_t total = s->jc_off + Layout::up(sizeof(unsigned long long) * 2 * static_cast<size_t>(max_jobs));
+    const size_t total = server_bytes(arena_bytes, max_jobs);
     if (o.workspace) {
         if (o.workspace_bytes < total) return bail(fail(PT_ENOMEM, "workspace of %zu B < %zu B", o.workspace_bytes, total));
         s->mem = static_cast<unsigned char *>(o.workspace);
@@ -515,10 +528,16 @@ pt_status pt_server_start(pt_server **out, size_t arena_bytes, int32_t max_jobs,
     }
     s->d_ctl = reinterpret_cast<JobControl *>(s->mem + s->ctl_off);
     s->d_jc = reinterpret_cast<unsigned long long *>(s->mem + s->jc_off);
-    if (hipHostMalloc(&s->h_ctl, 256, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc(&s->h_done, sizeof(int32_t) * max_jobs, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc(&s->h_slots, sizeof(JobSlot) * max_jobs, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc(&s->h_T, sizeof(double) * kServerMaxR * max_jobs, hipHostMallocDefault) != hipSuccess)
+    // The running kernel polls these words and reads the job table while the
+    // host writes them, so they must be coherent during the launch: default
+    // pinned memory (coherent only at dispatch boundaries unless the
+    // HIP_HOST_COHERENT environment variable says otherwise) may serve the
+    // device stale lines.
+    constexpr unsigned kCoh = hipHostMallocCoherent;
+    if (hipHostMalloc(&s->h_ctl, 256, kCoh) != hipSuccess ||
+        hipHostMalloc(&s->h_done, sizeof(int32_t) * max_jobs, kCoh) != hipSuccess ||
+        hipHostMalloc(&s->h_slots, sizeof(JobSlot) * max_jobs, kCoh) != hipSuccess ||
+        hipHostMalloc(&s->h_T, sizeof(double) * kServerMaxR * max_jobs, kCoh) != hipSuccess)
         return bail(fail(PT_ENOMEM, "pinned host allocation failed"));
     std::memset(s->h_ctl, 0, 256);
     std::memset(s->h_done, 0, sizeof(int32_t) * max_jobs);
@@ -546,6 +565,14 @@ pt_status pt_server_start(pt_server **out, size_t arena_bytes, int32_t max_jobs,
     s->t0 = now_s();
     s->th = std::thread(server_loop, s);
     *out = s;
+    return PT_OK;
+}
+
+pt_status pt_server_workspace_size(size_t arena_bytes, int32_t max_jobs, size_t *bytes)
+{
+    if (!bytes) return fail(PT_EINVAL, "bytes is NULL");
+    if (max_jobs < 1) return fail(PT_EINVAL, "max_jobs must be >= 1");
+    *bytes = server_bytes(arena_bytes, max_jobs);
     return PT_OK;
 }
 

@@ -16,9 +16,10 @@
 //
 // A static batch has a fixed job count and its table in device memory,
 // written before the launch.  A server keeps publishing jobs while the launch
-// runs: its job table and ladders live in pinned host memory, written by the
-// host before it raises the published count (host memory is coherent with the
-// device, unlike host copies into device memory during a launch).  Nothing the
+// runs: its job table and ladders live in coherent (fine-grained) pinned host
+// memory, written by the host before it raises the published count (such
+// memory is coherent with a running kernel, unlike host copies into device
+// memory during a launch, or default pinned memory).  Nothing the
 // device reads of a job comes from such a copy: the ready/finished words are one
 // pair per slot, never reused and cleared before the launch, and the counters
 // in the job's (reused) arena block are cleared by the device itself.
@@ -85,10 +86,8 @@ __device__ __forceinline__ void run_job_walker(const JobSlot &S, int w, unsigned
         __syncthreads();
         // the same sums, in the same order, as a single instance's k_setup
         setup_couplings(P, table_prec<F>());
-        if (tid == 0) {
-            __threadfence();
-            __hip_atomic_store(&jc[0], 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        release_all_agent();  // every thread's part of the set-up, before the ready flag
+        if (tid == 0) __hip_atomic_store(&jc[0], 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (tid == 0) {
         int ok = 1;
@@ -100,10 +99,9 @@ __device__ __forceinline__ void run_job_walker(const JobSlot &S, int w, unsigned
                 break;
             }
         }
-        __threadfence();
         sflag[0] = ok;
     }
-    __syncthreads();
+    acquire_all_agent();  // walker 0's set-up, in every thread
     bool ok = sflag[0] != 0;
     if (ok) {
         P.bound_init = __hip_atomic_load(&P.bnd->init, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -131,6 +129,10 @@ __device__ __forceinline__ void run_job_walker(const JobSlot &S, int w, unsigned
         __syncthreads();
         ok = run_walker<F, QT, PL, J64L>(P, plan, lds, w, 0, static_cast<int32_t>(S.sweeps), S.xevery, 0, 0, true);
     }
+    // every thread's final writes of this walker visible to the host (which
+    // copies the job's results once its last walker is counted)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+    __syncthreads();
     if (tid == 0) {
         if (!ok) atomicOr(&P.ctr[kCtrError], kErrBarrierTimeout);
         __threadfence_system();

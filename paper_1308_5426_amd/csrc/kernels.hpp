@@ -44,6 +44,14 @@ const void *sweep_fn_j(int q, const LdsPlan &p)
 template <typename F>
 const void *sweep_fn(int q, const LdsPlan &p)
 {
+    if constexpr (table_prec<F>() != kPrecF32) {  // overlapped sweep: FP64 / int32 table in LDS, q <= 4
+        if (p.ovl) {
+            if constexpr (table_prec<F>() == kPrecF64)
+                return reinterpret_cast<const void *>(&k_sweep<F, 4, kPlLds, true, true>);
+            else
+                return reinterpret_cast<const void *>(&k_sweep<F, 4, kPlLds, false, true>);
+        }
+    }
     switch (p.place) {
     case kPlLds: return sweep_fn_j<F, kPlLds>(q, p);
     case kPlHbm: return sweep_fn_j<F, kPlHbm>(q, p);

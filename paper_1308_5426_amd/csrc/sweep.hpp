@@ -39,6 +39,7 @@ struct LdsPlan {
     int32_t sfirst;       // [waves][L] u32 first-guessed-flip tables, or -1 when they do not fit
     int32_t xpart;        // [2][waves][64] FP64 partial corrections exchanged between waves
     int32_t ctab;         // [64][4] flush coefficients (table precision) by flip kind
+    int32_t ovl;          // 1: overlapped sweep (chain in the first half of the waves, flush in the second)
 };
 
 // Where a walker's field table lives during its sweeps (values of
@@ -89,6 +90,8 @@ struct Walker {
     double *xpart;      // [2][waves][64] partial corrections of the split passes
     F *ctab;            // [64][4] row coefficients of a flip of kind old + 16 new (states < 4)
     ChainState *cs;
+    uint32_t *gbar;     // [2] arrivals and generation of the chain waves' LDS barrier (overlapped sweep)
+    unsigned long long *err;  // the instance's error bits (bounded waits)
     int32_t chunk;
 };
 
@@ -120,6 +123,8 @@ __device__ __forceinline__ Walker<F> carve(unsigned char *lds, const LdsPlan &p,
     W.sfirst = p.sfirst >= 0 ? reinterpret_cast<uint32_t *>(lds + p.sfirst) : nullptr;
     W.xpart = reinterpret_cast<double *>(lds + p.xpart);
     W.ctab = reinterpret_cast<F *>(lds + p.ctab);
+    W.gbar = reinterpret_cast<uint32_t *>(W.misc + 4);
+    W.err = P.ctr + kCtrError;
     W.chunk = p.chunk;
     return W;
 }
@@ -195,8 +200,10 @@ __device__ __forceinline__ void load_walker(const Inst &P, Walker<F> &W, const L
         W.sp[j] = ssrc[j];
         if (J64l) J64l[j] = P.J64[j];
     }
+    const int chain_waves = static_cast<int>(blockDim.x / kWave) / (plan.ovl ? 2 : 1);
     if (W.sfirst)
-        for (int k = threadIdx.x; k < (blockDim.x / kWave) * L; k += blockDim.x) W.sfirst[k] = kWave;
+        for (int k = threadIdx.x; k < chain_waves * L; k += blockDim.x) W.sfirst[k] = kWave;
+    if (threadIdx.x < 2) W.gbar[threadIdx.x] = 0u;
     // coefficient of row c under a flip ap -> bp, kind ap + 16 bp (kind 0: no flip)
     for (int e = threadIdx.x; e < 256; e += blockDim.x) {
         const int k = e >> 2, c = e & 3;
@@ -340,6 +347,7 @@ __device__ void exchange_step(const Inst &P, int64_t m, XScratch X, double *red)
     __syncthreads();
     for (int g = 0; g < 2; ++g) {
         const int npair = (R - g) / 2;
+        bool unsure = false;
         for (int p = tid; p < npair; p += NT) {
             const int k = g + 2 * p;
             const int wa = X.perm[k], wb = X.perm[k + 1];
@@ -352,9 +360,10 @@ __device__ void exchange_step(const Inst &P, int64_t m, XScratch X, double *red)
             const double band = fabs(db) * (X.Eerr[wa] + X.Eerr[wb]);
             X.lnu[k] = lnu;
             X.dec[k] = (band > 0.0 && fabs(y) <= band + kBand + kEvalMargin) ? 2 : (y < 0.0 ? 1 : 0);
+            unsure |= X.dec[k] == 2;
         }
-        __syncthreads();
-        for (int p = 0; p < npair; ++p) {  // rare: uncertain pairs, whole workgroup
+        // rare: uncertain pairs, whole workgroup (skipped when there are none)
+        for (int p = 0, any = __syncthreads_or(unsure ? 1 : 0); any && p < npair; ++p) {
             const int k = g + 2 * p;
             if (X.dec[k] != 2) continue;
             for (int side = 0; side < 2; ++side) {
@@ -385,11 +394,12 @@ __device__ void exchange_step(const Inst &P, int64_t m, XScratch X, double *red)
                 atomicAdd(&P.ctr[kCtrBandedEx], 1ull);
                 log_event(P, 1, m, g, k, acc, y);
             }
-            P.xatt[k] += 1;
+            // counts without a read on the critical path (each pair has one thread)
+            atomicAdd(reinterpret_cast<unsigned long long *>(&P.xatt[k]), 1ull);
             if (acc) {
                 X.perm[k] = wb;
                 X.perm[k + 1] = wa;
-                P.xacc[k] += 1;
+                atomicAdd(reinterpret_cast<unsigned long long *>(&P.xacc[k]), 1ull);
             }
         }
         __syncthreads();
@@ -416,26 +426,39 @@ __device__ void exchange_step(const Inst &P, int64_t m, XScratch X, double *red)
 __device__ __forceinline__ unsigned *bar_count(const Inst &P) { return reinterpret_cast<unsigned *>(&P.ctr[kCtrBarCount]); }
 __device__ __forceinline__ unsigned *bar_gen(const Inst &P) { return reinterpret_cast<unsigned *>(&P.ctr[kCtrBarGen]); }
 
-__device__ bool grid_arrive(const Inst &P, int32_t *flag)
+// Every thread's global writes are made visible device-wide (a release fence
+// in each thread: on gfx9 one thread's fence writes back its XCD's L2, but
+// stores of the other waves may not have reached it yet) before one thread
+// signals; after a signal is observed, every thread takes the acquire (each
+// wave's caches invalidated) before reading what other workgroups wrote.
+__device__ __forceinline__ void release_all_agent()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+}
+__device__ __forceinline__ void acquire_all_agent()
 {
     __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+__device__ bool grid_arrive(const Inst &P, int32_t *flag)
+{
+    release_all_agent();  // spins and energies of this walker, for the exchange
     if (threadIdx.x == 0) {
-        __threadfence();
         const unsigned g = __hip_atomic_load(bar_gen(P), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
         const unsigned old = __hip_atomic_fetch_add(bar_count(P), 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         flag[0] = old == static_cast<unsigned>(P.R) - 1u;
         flag[1] = static_cast<int32_t>(g);
-        if (flag[0]) __threadfence();
     }
-    __syncthreads();
+    acquire_all_agent();  // the last to arrive reads every walker's data
     return flag[0] != 0;
 }
 
 __device__ void grid_release(const Inst &P, int32_t *flag)
 {
-    __syncthreads();
+    release_all_agent();  // the exchange's permutation, slots, energies and counts
     if (threadIdx.x == 0) {
-        __threadfence();
         __hip_atomic_store(bar_count(P), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(bar_gen(P), static_cast<unsigned>(flag[1]) + 1u, __ATOMIC_RELEASE,
                            __HIP_MEMORY_SCOPE_AGENT);
@@ -461,10 +484,9 @@ __device__ bool grid_wait(const Inst &P, int32_t *flag)
                 break;
             }
         }
-        __threadfence();
         flag[2] = ok;
     }
-    __syncthreads();
+    acquire_all_agent();  // the exchange's results, in every thread
     return flag[2] != 0;
 }
 
@@ -632,32 +654,81 @@ __device__ __forceinline__ uint32_t compact_flips(uint64_t set, int lane, uint32
 // Passes shorter than this run whole in every wave; longer ones are split.
 constexpr int kSplitMin = 8;
 
-// dE += the corrections of flips lst[begin..end), computed by the whole
-// workgroup.  Every wave holds the same 64 attempts; a short pass runs whole
-// in each wave (no exchange), a long one is split into contiguous shares, one
-// per wave, whose partial sums are exchanged through LDS (one barrier; the
-// buffer alternates between passes so a wave still reading one pass's
-// partials is never overwritten) and added in wave order, identically in
-// every wave.  Rounding of the split form: each partial is a difference of
+// Waves that run the chain: every wave of the workgroup, or (GRP, the
+// overlapped sweep) the first half, while the second half flushes.
+template <bool GRP>
+__device__ __forceinline__ int chain_nw()
+{
+    return static_cast<int>(blockDim.x / kWave) / (GRP ? 2 : 1);
+}
+
+// Barrier of the first nw waves of the workgroup through two LDS words
+// (arrivals, generation): lane 0 of each wave reads the generation, arrives;
+// the last to arrive clears the count and advances the generation, the others
+// wait for it to advance.  The rest of the workgroup takes no part.  The wait
+// is bounded: past kBarrierTicks of wall clock, or once any error bit is set,
+// it sets the time-out bit in err and stops waiting (the host then reports
+// the launch as failed).
+__device__ __forceinline__ void group_barrier(uint32_t *bar, uint32_t nw, unsigned long long *err)
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        const uint32_t g = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (__hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) == nw - 1u) {
+            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_store(&bar[1], g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        } else {
+            const uint64_t t0 = wall_clock64();
+            for (uint32_t k = 1; __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) == g; ++k) {
+                __builtin_amdgcn_s_sleep(1);
+                if ((k & 4095u) == 0u &&
+                    (wall_clock64() - t0 > kBarrierTicks ||
+                     __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0ull)) {
+                    atomicOr(err, kErrBarrierTimeout);
+                    break;
+                }
+            }
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+template <bool GRP, typename F>
+__device__ __forceinline__ void chain_sync(const Walker<F> &W)
+{
+    if constexpr (GRP)
+        group_barrier(W.gbar, static_cast<uint32_t>(chain_nw<true>()), W.err);
+    else
+        __syncthreads();
+}
+
+// dE += the corrections of flips lst[begin..end), each counted for the lanes
+// past its own (gate: the caller's lane; kWave counts every flip), computed by
+// the chain's waves.  Every wave holds the same 64 attempts; a short pass runs
+// whole in each wave (no exchange), a long one is split into contiguous
+// shares, one per wave, whose partial sums are exchanged through LDS (one
+// barrier; the buffer alternates between passes so a wave still reading one
+// pass's partials is never overwritten) and added in wave order, identically
+// in every wave.  Rounding of the split form: each partial is a difference of
 // two intermediate dE values (|.| <= 2 S), so the nw - 1 additions of
 // partials and the final addition add at most 2 units of 2 unit, counted in ex.
-template <typename F, bool D, bool NEG = false>
-__device__ __forceinline__ void add_flips_wg(const Walker<F> &W, int L, int i, int lane, uint32_t code, uint32_t lst,
+template <typename F, bool D, bool NEG = false, bool GRP = false>
+__device__ __forceinline__ void add_flips_wg(const Walker<F> &W, int L, int i, int gate, uint32_t code, uint32_t lst,
                                              int begin, int end, double &dE, int &ex, int &pbuf)
 {
-    const int nw = blockDim.x / kWave, wv = threadIdx.x / kWave;
+    const int nw = chain_nw<GRP>(), wv = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
     const int n = end - begin;
     if (nw == 1 || n < kSplitMin) {
-        apply_list<F, D, NEG>(W, L, i, lane, code, lst, begin, end, dE);
+        apply_list<F, D, NEG>(W, L, i, gate, code, lst, begin, end, dE);
         return;
     }
     const int per = (n + nw - 1) / nw;
     const int b0 = min(end, begin + wv * per), b1 = min(end, b0 + per);
     double part = 0.0;
-    apply_list<F, D, NEG>(W, L, i, lane, code, lst, b0, b1, part);
+    apply_list<F, D, NEG>(W, L, i, gate, code, lst, b0, b1, part);
     double *xp = W.xpart + pbuf * nw * kWave;
     xp[wv * kWave + lane] = part;
-    __syncthreads();
+    chain_sync<GRP>(W);
     double tot = xp[lane];
     for (int k = 1; k < nw; ++k) tot += xp[k * kWave + lane];
     pbuf ^= 1;
@@ -674,25 +745,21 @@ __device__ __forceinline__ double dE_now(const Walker<F> &W, int L, int a, int b
     double dE = static_cast<double>(W.h[a * L + i]) - static_cast<double>(W.h[b * L + i]);
     const uint32_t pv = lane < np ? W.pend[lane] : kNoFlip;
     ex = 0;
-    // lane 64 in the gate: every listed flip counts
-    const int nw = blockDim.x / kWave;
-    if (nw == 1 || np < kSplitMin) {
-        apply_list<F, D>(W, L, i, kWave, state_code(a, b), pv, 0, np, dE);
-    } else {
-        const int wv = threadIdx.x / kWave, per = (np + nw - 1) / nw;
-        const int b0 = min(np, wv * per), b1 = min(np, b0 + per);
-        double part = 0.0;
-        apply_list<F, D>(W, L, i, kWave, state_code(a, b), pv, b0, b1, part);
-        double *xp = W.xpart + pbuf * nw * kWave;
-        xp[wv * kWave + lane] = part;
-        __syncthreads();
-        double tot = xp[lane];
-        for (int k = 1; k < nw; ++k) tot += xp[k * kWave + lane];
-        pbuf ^= 1;
-        dE += tot;
-        ex = 2;
-    }
+    add_flips_wg<F, D>(W, L, i, kWave, state_code(a, b), pv, 0, np, dE, ex, pbuf);
     return dE;
+}
+
+// Overlapped sweep: a window's fields for every state at its sites, read
+// before the previous window's flush starts, and that window's flip list.
+struct Snap {
+    double v[4];     // h[c][i], c < q <= 4 (table units)
+    uint32_t prev;   // lane r: the previous window's r-th flip word
+    int nprev;
+};
+
+__device__ __forceinline__ double sel4(const double (&v)[4], int k)
+{
+    return k == 0 ? v[0] : (k == 1 ? v[1] : (k == 2 ? v[2] : v[3]));
 }
 
 // Direct energy changes (no field table): dE of every lane's attempt,
@@ -758,9 +825,9 @@ __device__ __forceinline__ double direct_dE_window(const Walker<F> &W, int L, in
 // flip, so Bd = 2 (init + nupd * unit) grown by 2 unit per flip bounds its
 // error exactly as for two separately kept fields; a split pass adds `ex`
 // more such units per lane.
-template <typename F, bool D, bool DIR>
+template <typename F, bool D, bool DIR, bool GRP = false>
 __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w, int64_t n, double beta_r, int t0,
-                                             int c0, int cend, ChainRegs &cr, int &pbuf)
+                                             int c0, int cend, ChainRegs &cr, int &pbuf, const Snap *snap = nullptr)
 {
     constexpr bool kF64 = sizeof(F) == sizeof(double);
     constexpr bool kI32 = table_prec<F>() == kPrecI32;
@@ -778,12 +845,18 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
     int b = a + kk;
     b -= b >= q ? q : 0;
     double dE;
-    if constexpr (DIR)
-        dE = direct_dE_window(W, L, i, a, b, pbuf);
-    else
-        dE = static_cast<double>(W.h[a * L + i]) - static_cast<double>(W.h[b * L + i]);
-    uint32_t code = state_code(a, b);
     int ex = 0;  // extra roundings in this lane's dE, in units of 2 unit
+    if constexpr (DIR) {
+        dE = direct_dE_window(W, L, i, a, b, pbuf);
+    } else if constexpr (GRP) {
+        // the snapshot (the table before the previous window's flush) plus that
+        // window's flips, all earlier than this window's attempts
+        dE = sel4(snap->v, a) - sel4(snap->v, b);
+        add_flips_wg<F, D, false, GRP>(W, L, i, kWave, state_code(a, b), snap->prev, 0, snap->nprev, dE, ex, pbuf);
+    } else {
+        dE = static_cast<double>(W.h[a * L + i]) - static_cast<double>(W.h[b * L + i]);
+    }
+    uint32_t code = state_code(a, b);
     uint64_t live = ballot(valid);
     int np = 0;
     double Bd = 2.0 * (P.bound_init + static_cast<double>(cr.nupd) * P.bound_unit);
@@ -820,7 +893,7 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
         const double dE0 = dE;
         const int ex0 = ex;
         const uint32_t lst = compact_flips(S, lane, pk);  // lane r: the r-th guessed flip
-        add_flips_wg<F, D>(W, L, i, lane, code, lst, 0, __popcll(S), dE, ex, pbuf);
+        add_flips_wg<F, D, false, GRP>(W, L, i, lane, code, lst, 0, __popcll(S), dE, ex, pbuf);
         // check: each lane decides with the guessed flips before it
         const double x = beta * dE + lnu;
         const int r = __popcll(S & mine_below);
@@ -880,9 +953,9 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
             if (nc <= ns - nc) {
                 dE = dE0;
                 ex = ex0;
-                add_flips_wg<F, D>(W, L, i, lane, code, lst, 0, nc, dE, ex, pbuf);
+                add_flips_wg<F, D, false, GRP>(W, L, i, lane, code, lst, 0, nc, dE, ex, pbuf);
             } else {
-                add_flips_wg<F, D, true>(W, L, i, lane, code, lst, nc, ns, dE, ex, pbuf);
+                add_flips_wg<F, D, true, GRP>(W, L, i, lane, code, lst, nc, ns, dE, ex, pbuf);
                 ex += 2 * max(0, r - nc);
             }
             if (accept) {
@@ -923,6 +996,14 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
                     const double t = chain_direct_dE(W, L, rl_i(i, g), rl_i(sn, g), rl_i(b2, g));
                     dE2 = lane == g ? t : dE2;
                 }
+            } else if constexpr (GRP) {
+                // snapshot + the previous window's flips + this window's first np
+                const int a2 = redo ? sn : a, bb = redo ? b2 : b;
+                dE2 = sel4(snap->v, a2) - sel4(snap->v, bb);
+                add_flips_wg<F, D, false, GRP>(W, L, i, kWave, state_code(a2, bb), snap->prev, 0, snap->nprev, dE2, ex2,
+                                               pbuf);
+                const uint32_t pv = lane < np ? W.pend[lane] : kNoFlip;
+                add_flips_wg<F, D, false, GRP>(W, L, i, kWave, state_code(a2, bb), pv, 0, np, dE2, ex2, pbuf);
             } else {
                 dE2 = dE_now<F, D>(W, L, redo ? sn : a, redo ? b2 : b, i, np, ex2, pbuf);
             }
@@ -936,12 +1017,13 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
         }
         // every wave has finished reading this iteration's spins before any
         // wave writes the next iteration's commits
-        if (blockDim.x > kWave) __syncthreads();
+        if (chain_nw<GRP>() > 1) chain_sync<GRP>(W);
     }
     if (lead && lane == 0) W.cs->np[(t0 / kWave) & 1] = np;
 }
 
-// Whole workgroup: apply the window's np flips to the table.  Each thread
+// Threads tid of NT (the whole workgroup, or the flush waves of an overlapped
+// sweep): apply the window's np flips to the table.  Each thread
 // owns M sites per pass and applies the flips to them in order, so no
 // barrier is needed between flips.  QT > 0 (q <= QT, QT = 4, 6 or 8): the
 // sites' fields of the rows the window's flips touch sit in registers for the
@@ -964,7 +1046,7 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
 // ones); its error against the exact change is at most the bound_flipE the
 // caller charges per flip.
 template <typename F, int QT, bool D>
-__device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np, double &part)
+__device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np, double &part, int tid, int NT)
 {
     constexpr int QR = QT > 0 ? QT : 1;  // rows held in registers (q <= QT)
     constexpr int M = kFlushM;             // register slots per thread
@@ -972,7 +1054,7 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
     constexpr bool kF32 = table_prec<F>() == kPrecF32;
     constexpr bool kI32 = table_prec<F>() == kPrecI32;
     using RT = typename std::conditional<kI32, double, F>::type;  // register arithmetic
-    const int L = P.L, tid = threadIdx.x, NT = blockDim.x, lane = tid & (kWave - 1);
+    const int L = P.L, lane = tid & (kWave - 1);  // threads tid of NT (whole waves) take part
     static_assert(kMaxSweepThreads <= 256 && kMaxJobThreads <= 256, "M sites per thread assume <= 256 threads");
     const uint32_t pv = lane < np ? W.pend[lane] : kNoFlip;  // the chain already wrote the spins
     // rows the window's flips touch (wave-uniform bits)
@@ -1137,7 +1219,7 @@ __device__ __forceinline__ double sweep_walker(const Inst &P, Walker<F> &W, int 
             ph_mark(ph, kPhChain);
             const int np = W.cs->np[(t0 / kWave) & 1];
             if (TAB && np > 0) {  // without a table the chain works from direct sums: nothing to flush
-                flush_window<F, QT, D>(P, W, np, part);
+                flush_window<F, QT, D>(P, W, np, part, threadIdx.x, blockDim.x);
                 __syncthreads();
                 ph_mark(ph, kPhFlush);
                 if (ph.on) ++ph.v[kPhFlushes];
@@ -1148,6 +1230,73 @@ __device__ __forceinline__ double sweep_walker(const Inst &P, Walker<F> &W, int 
             }
         }
     }
+    return part;
+}
+
+// One sweep with the chain and the flush overlapped (table in LDS, q <= 4,
+// the whole sweep's draws in one chunk; FP64 and int32 tables, whose flush
+// reads no spins).  The first half of the waves runs the chain, the second
+// half flushes.  Step s: the chain waves read window s's fields for every state
+// at its sites (the table as of window s - 2's flush); one workgroup barrier;
+// then the flush waves apply window s - 1's flips while the chain waves add
+// those same flips to their energy changes and run window s; one more barrier.
+// A window costs about the larger of its chain and the previous window's
+// flush instead of their sum.
+template <typename F, int QT>
+__device__ __forceinline__ double sweep_walker_ov(const Inst &P, Walker<F> &W, int w, int64_t n, double beta,
+                                                  ChainRegs &cr, PhaseAcc &ph)
+{
+    const int L = P.L, q = P.q, lane = threadIdx.x & (kWave - 1);
+    const int nc = chain_nw<true>();
+    const bool chainw = static_cast<int>(threadIdx.x / kWave) < nc;
+    uint32_t *const pend0 = W.pend;  // [2][64]: the flip lists of even and odd windows
+    double part = 0.0;
+    int pbuf = 0;
+    ph_start(ph);
+    gen_draws<F>(P, W, w, n, 0, L);
+    __syncthreads();
+    ph_mark(ph, kPhDraw);
+    const int nwin = (L + kWave - 1) / kWave;
+    int np_prev = 0;
+    // the chain's waves issue first on their SIMDs: it is the serial path
+    if (chainw) __builtin_amdgcn_s_setprio(3);
+    for (int s = 0; s <= nwin; ++s) {
+        const int t0 = s * kWave;
+        Snap sn;
+        sn.nprev = np_prev;
+        sn.prev = lane < np_prev ? pend0[((s - 1) & 1) * kWave + lane] : kNoFlip;
+        if (chainw && s < nwin) {
+            const int ta = t0 + lane;
+            const int i = ta < L ? static_cast<int>(W.draw[ta] & 0xFFFFu) : 0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) sn.v[c] = c < q ? static_cast<double>(W.h[c * L + i]) : 0.0;
+        }
+        __syncthreads();  // the snapshot is read before the flush below writes the table
+        if (chainw) {
+            if (s < nwin) {
+                W.pend = pend0 + (s & 1) * kWave;
+                chain_window<F, true, false, true>(P, W, w, n, beta, t0, 0, L, cr, pbuf, &sn);
+            }
+        } else if (np_prev > 0) {
+            if (ph.on) ph.t = clock64();
+            Walker<F> Wf = W;
+            Wf.pend = pend0 + ((s - 1) & 1) * kWave;
+            flush_window<F, QT, true>(P, Wf, np_prev, part, threadIdx.x - nc * kWave, nc * kWave);
+            ph_mark(ph, kPhFlush);
+            if (ph.on) ++ph.v[kPhFlushes];
+        }
+        __syncthreads();  // window s decided, window s - 1 flushed
+        np_prev = s < nwin ? W.cs->np[s & 1] : 0;
+        if (ph.on && threadIdx.x == 0) {
+            ph_mark(ph, kPhChain);
+            if (s < nwin) {
+                ++ph.v[kPhWindows];
+                ph.v[kPhFlips] += static_cast<uint64_t>(np_prev);
+            }
+        }
+    }
+    if (chainw) __builtin_amdgcn_s_setprio(0);
+    W.pend = pend0;
     return part;
 }
 
@@ -1255,7 +1404,7 @@ static __global__ void k_obs_by_slot(Inst P, double *__restrict__ Eslot, double 
 }
 
 template <typename F, int PL, bool J64L>
-__global__ __launch_bounds__(kMaxSweepThreads) void k_refresh(Inst P, LdsPlan plan)
+__global__ __launch_bounds__(2 * kMaxSweepThreads) void k_refresh(Inst P, LdsPlan plan)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     const int w = blockIdx.x;
@@ -1278,13 +1427,15 @@ __global__ __launch_bounds__(kMaxSweepThreads) void k_refresh(Inst P, LdsPlan pl
 // load its state into LDS, sweep, record, refresh on schedule, and (fused)
 // meet the instance's other walkers at the device barrier for the exchange.
 // Returns false if the barrier timed out.
-template <typename F, int QT, int PL, bool J64L>
+template <typename F, int QT, int PL, bool J64L, bool OV = false>
 __device__ __forceinline__ bool run_walker(const Inst &P, const LdsPlan &plan, unsigned char *lds, int w, int64_t n0,
                                            int32_t nsw, int32_t xevery, int32_t x0, int64_t m0, bool fused)
 {
     const int tid = threadIdx.x;
     PhaseAcc ph;
-    ph.on = P.phase != nullptr && tid == 0;
+    // thread 0 keeps the phases; in an overlapped sweep the flush waves' first
+    // thread keeps the flush's own cycles
+    ph.on = P.phase != nullptr && (tid == 0 || (OV && tid == static_cast<int>(blockDim.x) / 2));
     for (int k = 0; k < kPhN; ++k) ph.v[k] = 0;
     const uint64_t t_begin = ph.on ? clock64() : 0;
     constexpr bool TAB = PL != kPlDirect;
@@ -1299,7 +1450,11 @@ __device__ __forceinline__ bool run_walker(const Inst &P, const LdsPlan &plan, u
         const int slot = __hip_atomic_load(&P.slot_of[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const double beta = P.beta[slot];
         cr.nacc = 0;
-        const double part = sweep_walker<F, QT, PL>(P, W, w, n, beta, cr, ph);
+        double part;
+        if constexpr (OV)
+            part = sweep_walker_ov<F, QT>(P, W, w, n, beta, cr, ph);
+        else
+            part = sweep_walker<F, QT, PL>(P, W, w, n, beta, cr, ph);
         ph_start(ph);
         // energy change of the sweep: the flush's sums over the FP32 couplings
         // (FP32 table) or the accepted flips' dE held by the chain lanes (FP64
@@ -1352,21 +1507,26 @@ __device__ __forceinline__ bool run_walker(const Inst &P, const LdsPlan &plan, u
         P.nupd[w] = cr.nupd;
     }
     if (ph.on) {
-        ph.v[kPhTotal] = clock64() - t_begin;
-        ph.v[kPhIters] = cr.iters;
         unsigned long long *dst = P.phase + static_cast<size_t>(w) * kPhN;
-        for (int k = 0; k < kPhN; ++k) dst[k] += ph.v[k];
+        if (tid == 0) {
+            ph.v[kPhTotal] = clock64() - t_begin;
+            ph.v[kPhIters] = cr.iters;
+            for (int k = 0; k < kPhN; ++k) atomicAdd(&dst[k], ph.v[k]);
+        } else {  // the flush waves' counter (overlapped sweep)
+            atomicAdd(&dst[kPhFlush], ph.v[kPhFlush]);
+            atomicAdd(&dst[kPhFlushes], ph.v[kPhFlushes]);
+        }
     }
     __syncthreads();
     return true;
 }
 
-template <typename F, int QT, int PL, bool J64L>
-__global__ __launch_bounds__(kMaxSweepThreads) void k_sweep(Inst P, LdsPlan plan, int64_t n0, int32_t nsw,
-                                                            int32_t xevery, int32_t x0, int64_t m0, int32_t fused)
+template <typename F, int QT, int PL, bool J64L, bool OV = false>
+__global__ __launch_bounds__(OV ? 2 * kMaxSweepThreads : kMaxSweepThreads) void k_sweep(
+    Inst P, LdsPlan plan, int64_t n0, int32_t nsw, int32_t xevery, int32_t x0, int64_t m0, int32_t fused)
 {
     extern __shared__ __align__(16) unsigned char lds[];
-    (void)run_walker<F, QT, PL, J64L>(P, plan, lds, blockIdx.x, n0, nsw, xevery, x0, m0, fused != 0);
+    (void)run_walker<F, QT, PL, J64L, OV>(P, plan, lds, blockIdx.x, n0, nsw, xevery, x0, m0, fused != 0);
 }
 
 static __global__ __launch_bounds__(1024) void k_exchange(Inst P, int64_t m)

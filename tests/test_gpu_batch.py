@@ -134,18 +134,20 @@ def test_server_results_equal_alone(pkg, orc):
     """Jobs submitted while others run; each equals the oracle run alone."""
     jobs = _jobs(16, seed=21, lmax=400, rmax=16)
     srv = pkg.Server(arena_bytes=64 << 20, max_jobs=64)
-    ids = []
-    for k, job in enumerate(jobs):
-        ids.append(srv.submit(job))
-        if k % 4 == 3:
-            time.sleep(0.01)
-    for jid, job in zip(ids, jobs):
-        obs = srv.wait(jid, timeout=120)
-        s, p = srv.spins(jid)
-        _check_job(orc, job, s, p, obs)
-        t_sub, t_adm, t_fin = srv.times(jid)
-        assert t_sub <= t_adm <= t_fin
-    srv.stop()
+    try:  # a server left running keeps every CU: stop it whatever happens
+        ids = []
+        for k, job in enumerate(jobs):
+            ids.append(srv.submit(job))
+            if k % 4 == 3:
+                time.sleep(0.01)
+        for jid, job in zip(ids, jobs):
+            obs = srv.wait(jid, timeout=120)
+            s, p = srv.spins(jid)
+            _check_job(orc, job, s, p, obs)
+            t_sub, t_adm, t_fin = srv.times(jid)
+            assert t_sub <= t_adm <= t_fin
+    finally:
+        srv.stop()
 
 
 def test_server_admission_by_memory(pkg, orc):
@@ -156,25 +158,33 @@ def test_server_admission_by_memory(pkg, orc):
                  exchange_every=1, init=0) for j in range(4)]
     one = 16 * 512 * 4 * 8 + 16 * 512 + (1 << 16)
     srv = pkg.Server(arena_bytes=one + (one // 2), max_jobs=8)
-    ids = [srv.submit(j) for j in jobs]
-    for jid, job in zip(ids, jobs):
-        obs = srv.wait(jid, timeout=120)
-        s, p = srv.spins(jid)
-        _check_job(orc, job, s, p, obs)
-    adm = [srv.times(i)[1] for i in ids]
-    fin = [srv.times(i)[2] for i in ids]
-    for k in range(1, len(ids)):
-        assert adm[k] >= fin[k - 1] - 1e-3  # admitted only after the previous job freed its memory
-    srv.stop()
+    try:
+        ids = [srv.submit(j) for j in jobs]
+        for jid, job in zip(ids, jobs):
+            obs = srv.wait(jid, timeout=120)
+            s, p = srv.spins(jid)
+            _check_job(orc, job, s, p, obs)
+        adm = [srv.times(i)[1] for i in ids]
+        fin = [srv.times(i)[2] for i in ids]
+        for k in range(1, len(ids)):
+            assert adm[k] >= fin[k - 1] - 1e-3  # admitted only after the previous job freed its memory
+    finally:
+        srv.stop()
 
 
 def test_server_rejects_bad_jobs(pkg):
     srv = pkg.Server(arena_bytes=1 << 20, max_jobs=4)
+    try:
+        _rejects(pkg, srv)
+    finally:
+        srv.stop()
+
+
+def _rejects(pkg, srv):
     with pytest.raises(pkg.PTError):
         srv.submit(dict(L=10, q=3, sigma=0.0, T=[1.0], seed=1, sweeps=1))
     with pytest.raises(pkg.PTError):
         srv.submit(dict(L=10, q=3, sigma=0.5, T=np.linspace(0.5, 2.0, 65), seed=1, sweeps=1))
-    srv.stop()
 
 
 @pytest.mark.parametrize("precision", [0, 1, 2])

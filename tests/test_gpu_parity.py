@@ -261,3 +261,37 @@ def test_large_config_all_walkers(pkg, orc, placement, precision):
     # here); FP32 table: energy changes summed from the FP32 couplings, 1e-6
     rtol = inst.L * inst.L / 2 * 2.0**-53 if (placement == 3 or precision == 0) else 1e-6
     np.testing.assert_allclose(obs["E"], ref.energies()[ref.perm()], rtol=rtol)
+
+
+@pytest.mark.parametrize("precision", [0, 2])
+@pytest.mark.parametrize("L,q", [(256, 2), (300, 3), (1000, 4), (1024, 3)])
+def test_overlapped_sweep_matches_oracle(pkg, orc, L, q, precision):
+    """The overlapped sweep (512 threads: chain of window s beside the flush of
+    window s - 1) against the oracle: identical trajectories, every window
+    with flips, fused exchange after each sweep."""
+    T = _ladder(0.25, 3.0, 12)
+    sim, ref = run_pair(pkg, orc, L, q, 0.45, T, 5 + L, 24, 1, precision=precision, threads=512, steps=2,
+                        mode=1)
+    assert sim.plan()["threads"] == 512
+    obs = _cmp_energy(sim, ref, 1e-6 if precision else 1e-11)
+    st = ref.stats()
+    np.testing.assert_array_equal(obs["flip_acc"], st["flip_acc"])
+    np.testing.assert_array_equal(obs["xchg_acc"], st["xchg_acc"])
+
+
+def test_overlapped_equals_plain_sweep(pkg):
+    """The 1024-site workload's shape with and without the overlap: the same
+    decisions, energies equal to the rounding of their different summation."""
+    T = _ladder(0.3, 3.0, 64)
+    out = []
+    for threads in (512, 256):
+        sim = pkg.Simulation(1024, 3, 0.4, T, 1234, threads=threads)
+        sim.run(30, 1)
+        out.append((sim.plan()["threads"], sim.spins(), sim.observables()))
+        sim.close()
+    (t1, (s1, p1), o1), (t2, (s2, p2), o2) = out
+    assert (t1, t2) == (512, 256)
+    np.testing.assert_array_equal(s1, s2)
+    np.testing.assert_array_equal(p1, p2)
+    np.testing.assert_array_equal(o1["flip_acc"], o2["flip_acc"])
+    np.testing.assert_allclose(o1["E"], o2["E"], rtol=1e-11)
