@@ -286,10 +286,12 @@ pt_status pt_batch_free(pt_batch *b);
 
 /* ------------------------------------------------------------------------ */
 /* Serving: a persistent launch that keeps taking jobs while it runs.      */
-/* Submitted jobs wait in a host queue until their state fits in the device */
-/* arena (admission by device memory), are then published to the running  */
-/* kernel, and their results are copied back when their last walker ends. */
-/* A host thread does the admission, publication and completion polling.   */
+/* Submitted jobs wait in a host queue, in order, until their state fits in */
+/* the device arena (admission by device memory) and the walkers admitted   */
+/* and not yet finished stay within twice the resident workgroups; they are */
+/* then published to the running kernel, and their results are copied back */
+/* when their last walker ends.  A host thread does the admission,          */
+/* publication and completion polling.                                      */
 /* ------------------------------------------------------------------------ */
 typedef struct pt_server pt_server;
 
@@ -308,6 +310,10 @@ pt_status pt_server_submit(pt_server *s, const pt_job_desc *job, int64_t *id_out
 pt_status pt_server_poll(pt_server *s, int64_t id, int32_t *done_out, pt_obs *out);
 /* Blocks until job id has finished (or timeout_s elapses: PT_ESTATE). */
 pt_status pt_server_wait(pt_server *s, int64_t id, double timeout_s, pt_obs *out);
+/* Cancels job id if it still waits in the host queue (PT_OK; poll then
+ * reports it ended and wait/poll/get_spins return PT_ESTATE for it); a job
+ * already admitted runs to its end (PT_ESTATE).  Thread-safe. */
+pt_status pt_server_cancel(pt_server *s, int64_t id);
 /* Host times of job id (seconds on a monotonic clock): submitted, admitted
  * (published to the device), finished (results copied back). */
 pt_status pt_server_times(pt_server *s, int64_t id, double *submitted, double *admitted, double *finished);

@@ -86,7 +86,7 @@ EXPORTS = [
     "pt_batch_workspace_size", "pt_batch_create", "pt_batch_run", "pt_batch_observables",
     "pt_batch_get_spins", "pt_batch_shape", "pt_batch_free",
     "pt_server_workspace_size", "pt_server_start", "pt_server_submit", "pt_server_poll", "pt_server_wait", "pt_server_times",
-    "pt_server_get_spins", "pt_server_stop", "pt_run_static",
+    "pt_server_get_spins", "pt_server_cancel", "pt_server_stop", "pt_run_static",
 ]
 STATIC_SCRATCH_BYTES = 64 << 20
 
@@ -143,6 +143,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.pt_server_poll.argtypes = [_P, i64, ctypes.POINTER(i32), OB]
     L.pt_server_wait.argtypes = [_P, i64, d, OB]
     L.pt_server_times.argtypes = [_P, i64, ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(d)]
+    L.pt_server_cancel.argtypes = [_P, i64]
     L.pt_server_get_spins.argtypes = [_P, i64, _P, _P]
     L.pt_server_stop.argtypes = [_P]
     L.pt_run_static.argtypes = [i32, i32, d, _P, i32, u64, i64, i32, OP, OB, _P, _P]
@@ -485,6 +486,15 @@ class Server:
         o, arrs, ints, pairs, perm = _obs_buffers(R)
         _check(self._lib.pt_server_wait(self._h, int(jid), float(timeout), ctypes.byref(o)))
         return _obs_dict(o, arrs, ints, pairs, perm, R)
+
+    def cancel(self, jid) -> bool:
+        """Drop a job still waiting in the host queue: True; False if it was
+        already admitted (it then runs to its end)."""
+        st = self._lib.pt_server_cancel(self._h, int(jid))
+        if st == PT_ESTATE:
+            return False
+        _check(st)
+        return True
 
     def times(self, jid):
         a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()

@@ -343,7 +343,7 @@ struct ServerJob {
     int32_t slot = -1;          // index in the job table once admitted
     size_t off = 0, bytes = 0;  // arena block
     double t_submit = 0, t_admit = 0, t_done = 0;
-    int state = 0;              // 0 queued, 1 running, 2 done, 3 failed
+    int state = 0;              // 0 queued, 1 running, 2 done, 3 failed, 4 cancelled
     HostObs obs;
     std::vector<uint8_t> spins;
 };
@@ -370,6 +370,7 @@ struct pt_server {
     int64_t next_id = 0;
     int32_t published = 0;
     int32_t wbase = 0;
+    int32_t inflight = 0, inflight_max = 0;  // walkers admitted and not yet finished
     bool quit = false, failed = false;
     std::string fail_msg;
     std::thread th;
@@ -412,12 +413,17 @@ void arena_free(pt_server *s, size_t off, size_t bytes)
     }
 }
 
-// Admit the queue's head jobs that fit, in order; publish them.
+// Admit the queue's head jobs that fit, in order; publish them.  A job is
+// admitted when its state fits in the arena and the walkers admitted and not
+// yet finished stay within inflight_max (or none are): the device always has
+// published tickets to take, and the rest of the backlog waits on the host,
+// where it can still be cancelled.
 bool server_admit(pt_server *s)
 {
     bool any = false;
     while (!s->queue.empty() && s->published < s->max_jobs) {
         ServerJob &J = s->jobs[s->queue.front()];
+        if (s->inflight > 0 && s->inflight + J.desc.R > s->inflight_max) break;
         size_t off = 0;
         if (!arena_alloc(s, J.bytes, &off)) break;  // head-of-line: wait for memory
         s->queue.pop_front();
@@ -433,6 +439,7 @@ bool server_admit(pt_server *s)
         job_slot(s->h_slots[J.slot], J.desc, s->prec, s->mem + off, Th, plan, variant, s->wbase,
                  s->d_jc + 2 * static_cast<size_t>(J.slot));
         s->wbase += J.desc.R;
+        s->inflight += J.desc.R;
         s->published += 1;
         J.state = 1;
         J.t_admit = now_s() - s->t0;
@@ -466,6 +473,7 @@ bool server_collect(pt_server *s, std::unique_lock<std::mutex> &lk)
         J.t_done = now_s() - s->t0;
         J.state = ok && J.obs.ctr[kCtrError] == 0 ? 2 : 3;
         arena_free(s, J.off, J.bytes);
+        s->inflight -= J.desc.R;
         s->running.erase(s->running.begin() + static_cast<long>(k));
         any = true;
     }
@@ -550,6 +558,7 @@ pt_status pt_server_start(pt_server **out, size_t arena_bytes, int32_t max_jobs,
     if (st != PT_OK) return bail(st);
     if (cap < kServerMaxR) return bail(fail(PT_EINVAL, "only %d workgroups fit at once (need %d)", cap, kServerMaxR));
     s->grid = cap;
+    s->inflight_max = 2 * cap;
     s->free_blocks[0] = s->arena_bytes;
     // ticket and every slot's ready/finished words start at zero with the launch
     if (zero_async(s->d_ctl, total - s->ctl_off, s->kstream) != PT_OK) return bail(PT_EDEVICE);
@@ -608,6 +617,7 @@ pt_status pt_server_submit(pt_server *s, const pt_job_desc *job, int64_t *id_out
 static pt_status server_result(pt_server *s, const ServerJob &J, pt_obs *out)
 {
     if (J.state == 3) return fail(PT_EDEVICE, "job %lld failed on the device", static_cast<long long>(J.id));
+    if (J.state == 4) return fail(PT_ESTATE, "job %lld was cancelled", static_cast<long long>(J.id));
     if (out) J.obs.fill(out, J.desc.sweeps, J.desc.sweeps / J.desc.exchange_every, J.desc.sweeps);
     (void)s;
     return PT_OK;
@@ -620,7 +630,7 @@ pt_status pt_server_poll(pt_server *s, int64_t id, int32_t *done, pt_obs *out)
     auto it = s->jobs.find(id);
     if (it == s->jobs.end()) return fail(PT_EINVAL, "unknown job id");
     const bool fin = it->second.state >= 2;
-    if (done) *done = fin ? 1 : 0;
+    if (done) *done = fin ? 1 : 0;  // cancelled jobs count as ended (and report PT_ESTATE)
     if (fin) return server_result(s, it->second, out);
     return PT_OK;
 }
@@ -638,6 +648,26 @@ pt_status pt_server_wait(pt_server *s, int64_t id, double timeout_s, pt_obs *out
             return fail(PT_ESTATE, "job %lld not finished after %.1f s", static_cast<long long>(id), timeout_s);
     }
     return server_result(s, it->second, out);
+}
+
+pt_status pt_server_cancel(pt_server *s, int64_t id)
+{
+    if (!s) return fail(PT_EINVAL, "null server");
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->jobs.find(id);
+    if (it == s->jobs.end()) return fail(PT_EINVAL, "unknown job id");
+    ServerJob &J = it->second;
+    if (J.state == 4) return PT_OK;
+    if (J.state != 0) return fail(PT_ESTATE, "job %lld was already admitted", static_cast<long long>(id));
+    for (auto q = s->queue.begin(); q != s->queue.end(); ++q)
+        if (*q == id) {
+            s->queue.erase(q);
+            break;
+        }
+    J.state = 4;
+    J.t_done = now_s() - s->t0;
+    s->cv.notify_all();
+    return PT_OK;
 }
 
 pt_status pt_server_times(pt_server *s, int64_t id, double *sub, double *adm, double *fin)

@@ -72,6 +72,7 @@ def test_host_only_calls():
     assert lib.pt_init(ctypes.byref(ctx), 10, 3, 0.5, ctypes.cast(T, ctypes.c_void_p), 2, 1, None) == pkg.PT_EINVAL
     assert b"ascending" in lib.pt_last_error()
     assert lib.pt_sweep(None, 1) == pkg.PT_EINVAL
+    assert lib.pt_server_cancel(None, 0) == pkg.PT_EINVAL
 
 
 def test_probe_library_exports():

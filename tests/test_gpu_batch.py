@@ -180,6 +180,36 @@ def test_server_rejects_bad_jobs(pkg):
         srv.stop()
 
 
+def test_server_cancel_queued_jobs(pkg):
+    """Jobs beyond the in-flight bound wait on the host and can be cancelled;
+    admitted jobs cannot, and every other job still completes."""
+    from workloads import geometric_ladder
+
+    T = geometric_ladder(0.3, 3.0, 64)
+    jobs = [dict(L=128, q=3, sigma=0.5, T=T, seed=700 + j, sweeps=4000, exchange_every=1, init=0) for j in range(24)]
+    srv = pkg.Server(arena_bytes=256 << 20, max_jobs=32)
+    try:
+        ids = [srv.submit(j) for j in jobs]
+        # 1536 walkers: at most twice the resident workgroups are admitted at once
+        assert not srv.cancel(ids[0])  # admitted at once (nothing was in flight)
+        for jid in ids[-4:]:
+            assert srv.cancel(jid)
+        assert srv.cancel(ids[-1])  # cancelling twice is harmless
+        for jid in ids[:-4]:
+            obs = srv.wait(jid, timeout=120)
+            assert obs["flip_att"].sum() == 128 * 64 * 4000
+        for jid in ids[-4:]:
+            with pytest.raises(pkg.PTError):
+                srv.poll(jid)
+            with pytest.raises(pkg.PTError):
+                srv.wait(jid, timeout=1)
+            with pytest.raises(pkg.PTError):
+                srv.spins(jid)
+        assert not srv.cancel(ids[1])  # finished
+    finally:
+        srv.stop()
+
+
 def _rejects(pkg, srv):
     with pytest.raises(pkg.PTError):
         srv.submit(dict(L=10, q=3, sigma=0.0, T=[1.0], seed=1, sweeps=1))
