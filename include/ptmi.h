@@ -65,7 +65,9 @@ enum { PT_PREC_F64 = 0, PT_PREC_F32 = 1, PT_PREC_I32 = 2 };
 enum { PT_INIT_RANDOM = 0, PT_INIT_ORDERED = 1 };
 /* Placement of a walker's field table during its sweeps: in LDS, in HBM
  * (couplings and spins in LDS), or no table at all (every energy change a
- * direct FP64 sum over the spins, the paper's own per-attempt scheme). */
+ * direct FP64 sum over the spins, the paper's own per-attempt scheme).  The
+ * table keeps q - 1 rows of L entries per walker: a site's q fields sum to the
+ * coupling sum, so the last row is formed from the others when read. */
 enum { PT_PLACE_AUTO = 0, PT_PLACE_LDS = 1, PT_PLACE_HBM = 2, PT_PLACE_DIRECT = 3 };
 
 /* Kernel limit on the number of Potts states. */

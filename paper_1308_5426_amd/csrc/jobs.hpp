@@ -29,12 +29,12 @@
 namespace ptmi {
 
 // Kernel variant of a job: placement of its field table (kPl*, bits 0-1), rows
-// held in registers by the flush (bits 2-3: 0 none, 1 four, 2 eight, 3 six)
-// and FP64 couplings in LDS (bit 4).
-constexpr int32_t kVarQtShift = 2, kVarJ64Lds = 16;
+// held in registers by the flush for the q - 1 stored rows (bits 2-4: 0 none,
+// 1 four, 2 eight, 3 six, 4 two) and FP64 couplings in LDS (bit 5).
+constexpr int32_t kVarQtShift = 2, kVarQtMask = 7, kVarJ64Lds = 32;
 __host__ __device__ inline int32_t job_variant(int place, int q, bool j64_in_lds)
 {
-    const int32_t qt = q <= 4 ? 1 : (q <= 6 ? 3 : (q <= 8 ? 2 : 0));
+    const int32_t qt = q <= 3 ? 4 : (q <= 4 ? 1 : (q <= 6 ? 3 : (q <= 8 ? 2 : 0)));
     return static_cast<int32_t>(place) | (qt << kVarQtShift) | (j64_in_lds ? kVarJ64Lds : 0);
 }
 
@@ -110,6 +110,9 @@ __device__ __forceinline__ void run_job_walker(const JobSlot &S, int w, unsigned
         P.bound_flipE = __hip_atomic_load(&P.bnd->flipE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         P.ebound = __hip_atomic_load(&P.bnd->ebound, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         P.qscale = __hip_atomic_load(&P.bnd->qscale, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        P.hsum = __hip_atomic_load(&P.bnd->hsum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        P.bound_rows = __hip_atomic_load(&P.bnd->rows, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        P.bound_impl = __hip_atomic_load(&P.bnd->impl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         for (int j = tid; j < L; j += blockDim.x)
             P.spins[static_cast<size_t>(w) * L + j] = initial_spin(P, w, j, S.init != 0);
         __syncthreads();
@@ -151,7 +154,8 @@ __device__ __forceinline__ void dispatch_qt(const JobSlot &S, int w, unsigned ch
     if constexpr (PL == kPlDirect) {
         run_job_walker<F, 0, PL, J64L>(S, w, lds, done_flag, sflag);
     } else {
-        switch ((S.variant >> kVarQtShift) & 3) {
+        switch ((S.variant >> kVarQtShift) & kVarQtMask) {
+        case 4: run_job_walker<F, 2, PL, J64L>(S, w, lds, done_flag, sflag); break;
         case 1: run_job_walker<F, 4, PL, J64L>(S, w, lds, done_flag, sflag); break;
         case 2: run_job_walker<F, 8, PL, J64L>(S, w, lds, done_flag, sflag); break;
         case 3: run_job_walker<F, 6, PL, J64L>(S, w, lds, done_flag, sflag); break;

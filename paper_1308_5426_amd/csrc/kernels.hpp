@@ -19,13 +19,16 @@ const void *jobs_kernel_f32();
 const void *jobs_kernel_i32();
 
 #ifdef PTMI_KERNEL_SELECT
-// Kernel variant by the number of states (four, six or eight flush rows in
-// registers for q <= 4, 6 or 8; row by row beyond), by where the field table
-// lives and by whether the FP64 couplings are in LDS.
+// Kernel variant by the number of states (two, four, six or eight flush rows
+// in registers for the q - 1 stored rows of q <= 3, 4, 6 or 8; row by row
+// beyond), by where the field table lives and by whether the FP64 couplings
+// are in LDS.  The two- and four-row forms read their coefficients from a
+// table that covers states below 4.
 template <typename F, int PL, bool J64L>
 const void *sweep_fn_q(int q)
 {
     if constexpr (PL == kPlDirect) return reinterpret_cast<const void *>(&k_sweep<F, 0, PL, J64L>);
+    if (q <= 3) return reinterpret_cast<const void *>(&k_sweep<F, 2, PL, J64L>);
     if (q <= 4) return reinterpret_cast<const void *>(&k_sweep<F, 4, PL, J64L>);
     if (q <= 6) return reinterpret_cast<const void *>(&k_sweep<F, 6, PL, J64L>);
     if (q <= 8) return reinterpret_cast<const void *>(&k_sweep<F, 8, PL, J64L>);

@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kReplayThreads) void k_flush_replay(int L, int q, i
             const int np = static_cast<int>(nwords - p0 < ptmi::kWave ? nwords - p0 : ptmi::kWave);
             if (threadIdx.x < ptmi::kWave) pend[threadIdx.x] = static_cast<int>(threadIdx.x) < np ? words[p0 + threadIdx.x] : ptmi::kNoFlip;
             __syncthreads();
-            ptmi::flush_window<double, 4, true>(P, W, np, part, threadIdx.x, blockDim.x);
+            ptmi::flush_window<double, 4, true>(P, W, np, part, threadIdx.x, blockDim.x, q);  // every row stored
             __syncthreads();
         }
     }

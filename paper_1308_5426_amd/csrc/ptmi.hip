@@ -102,7 +102,7 @@ bool make_plan_chunk(int L, int q, int R, int prec, bool fused, int place, size_
     p->J = o; o = align16(o + fb * p->jlen);
     p->h_in_lds = h_in_lds ? 1 : 0;
     p->h = o;
-    if (h_in_lds) o = align16(o + fb * q * L);
+    if (h_in_lds) o = align16(o + fb * (q - 1) * L);  // row q-1 is implicit
     p->sp = o; o = align16(o + L);
     p->cnt = o; o = align16(o + 4 * kQMax);
     p->red = o; o = align16(o + 8 * 32);
@@ -379,6 +379,9 @@ pt_status setup_instance(pt_ctx *c, const double *T)
     P.bound_flipE = b.flipE;
     P.ebound = b.ebound;
     P.qscale = b.qscale;
+    P.hsum = b.hsum;
+    P.bound_rows = b.rows;
+    P.bound_impl = b.impl;
     return PT_OK;
 }
 

@@ -65,20 +65,36 @@ enum : int { kPrecF64 = 0, kPrecF32 = 1, kPrecI32 = 2 };
 //         energy, tracked exactly in the quantised couplings, is off by at
 //         most L Dq / 2.
 // S = sum_r J*(r), Jmax = J*(1).
+//
+// The table keeps rows 0 .. q-2 only: a site's q fields sum to the coupling
+// sum of the table's own couplings, Stab (FP64 or FP32 couplings summed in
+// FP64, or the quantised ones, exactly), so row q-1 is Stab minus the others.
+// An energy change read from the table is a difference of two entries; when
+// one of them is the implicit row its error is at most that of q - 1 entries,
+// plus Stab's own error and q roundings of the subtraction (none for int
+// tables, whose sums are exact and whose implicit entry deviates from the
+// exact field by at most Dq like any other).  So the chain's starting bound is
+// rows (init + nupd unit) + impl with rows = q + 1 and impl = (L + q + 2) 2^-53
+// S (FP tables; rows = 2, impl = 0 for int32).
 struct TableBounds {
     double init, unit;
     int64_t nupd_max;
     double flipE, ebound, qscale;
+    double hsum;        // Stab in table units
+    double rows, impl;  // the chain's starting bound: rows (init + nupd unit) + impl
 };
 
 __host__ __device__ inline TableBounds table_bounds(double S, double Jmax, double D32, double Dq, int L, int prec,
-                                                    double qscale)
+                                                    double qscale, int q, double Stab)
 {
     const double u64 = 0x1p-53, Ld = static_cast<double>(L);
     TableBounds b;
     b.qscale = 1.0;
     b.flipE = 0.0;
     b.ebound = 0.0;
+    b.hsum = Stab;
+    b.rows = prec == kPrecI32 ? 2.0 : static_cast<double>(q + 1);
+    b.impl = prec == kPrecI32 ? 0.0 : (Ld + static_cast<double>(q) + 2.0) * u64 * S * 1.01;
     if (prec == kPrecI32) {
         b.qscale = qscale;
         b.init = Dq / qscale * 1.01;  // table units
@@ -120,11 +136,13 @@ struct Inst {
     double bound_flipE;        // energy error per accepted flip of an FP32 table (0 otherwise)
     double ebound;             // energy error right after a refresh (0: FP64 table)
     double qscale;             // real value of one table unit (2^-k for I32, else 1)
+    double hsum;               // sum of a site's q fields (table units): row q-1 = hsum - rows 0..q-2
+    double bound_rows, bound_impl;  // the chain's starting bound: rows (init + nupd unit) + impl
     const double *J64;         // [L]
     const float *J32;          // [L]
     const int32_t *Jq;         // [L] quantised couplings (I32 tables)
     uint8_t *spins;            // [R][L], states 0..q-1
-    void *h;                   // [R][q][L] field table backing store (double, float or int32)
+    void *h;                   // [R][q-1][L] field table backing store (double, float or int32)
     double *E, *Eerr;          // [R] tracked energy and a rigorous bound on its error
     int64_t *nupd;             // [R] flips applied to the table since its last refresh
     int32_t *counts;           // [R][kQMax] number of sites per state
@@ -160,7 +178,7 @@ struct Layout {
         J32 = take(sizeof(float) * L);
         Jq = take(sizeof(int32_t) * L);
         spins = take(static_cast<size_t>(R) * L);
-        h = take(fbytes * static_cast<size_t>(R) * q * L);
+        h = take(fbytes * static_cast<size_t>(R) * (q - 1) * L);  // row q-1 is implicit
         E = take(sizeof(double) * R);
         Eerr = take(sizeof(double) * R);
         nupd = take(sizeof(int64_t) * R);

@@ -76,7 +76,7 @@ constexpr uint64_t kBarrierTicks = 2000000000ull;
 template <typename F>
 struct Walker {
     F *J;               // [L] couplings in the table's precision
-    F *h;               // [q][L] field table
+    F *h;               // [q-1][L] field table (row q-1 implicit: the coupling sum minus the others)
     const double *J64;  // [L] FP64 couplings (LDS or HBM)
     uint8_t *sp;        // [L] spins 0..q-1
     int32_t *cnt;       // [kQMax]
@@ -106,7 +106,7 @@ __device__ __forceinline__ Walker<F> carve(unsigned char *lds, const LdsPlan &p,
     if constexpr (PL == kPlLds)
         W.h = reinterpret_cast<F *>(lds + p.h);
     else
-        W.h = static_cast<F *>(P.h) + static_cast<size_t>(w) * P.q * P.L;
+        W.h = static_cast<F *>(P.h) + static_cast<size_t>(w) * (P.q - 1) * P.L;
     if constexpr (J64L)
         W.J64 = reinterpret_cast<const double *>(lds + p.J64);
     else
@@ -193,7 +193,7 @@ __device__ __forceinline__ void load_walker(const Inst &P, Walker<F> &W, const L
 {
     const int L = P.L, q = P.q;
     const F *Jsrc = coupling_src<F>(P);
-    const F *hsrc = static_cast<const F *>(P.h) + static_cast<size_t>(w) * q * L;
+    const F *hsrc = static_cast<const F *>(P.h) + static_cast<size_t>(w) * (q - 1) * L;
     const uint8_t *ssrc = P.spins + static_cast<size_t>(w) * L;
     double *J64l = plan.j64_in_lds && sizeof(F) != sizeof(double) ? const_cast<double *>(W.J64) : nullptr;
     for (int j = threadIdx.x; j < L; j += blockDim.x) {
@@ -212,7 +212,7 @@ __device__ __forceinline__ void load_walker(const Inst &P, Walker<F> &W, const L
     // J[k] = J*(k mod L): with a doubled row, J*(|j - i|) = J[j - i + L] needs no wrap
     for (int k = threadIdx.x; k < plan.jlen; k += blockDim.x) W.J[k] = Jsrc[k % L];
     if (plan.h_in_lds)
-        for (int e = threadIdx.x; e < q * L; e += blockDim.x) W.h[e] = hsrc[e];
+        for (int e = threadIdx.x; e < (q - 1) * L; e += blockDim.x) W.h[e] = hsrc[e];
     if (threadIdx.x < kQMax) W.cnt[threadIdx.x] = P.counts[w * kQMax + threadIdx.x];
 }
 
@@ -220,11 +220,11 @@ template <typename F>
 __device__ __forceinline__ void store_walker(const Inst &P, const Walker<F> &W, const LdsPlan &plan, int w)
 {
     const int L = P.L, q = P.q;
-    F *hdst = static_cast<F *>(P.h) + static_cast<size_t>(w) * q * L;
+    F *hdst = static_cast<F *>(P.h) + static_cast<size_t>(w) * (q - 1) * L;
     uint8_t *sdst = P.spins + static_cast<size_t>(w) * L;
     for (int j = threadIdx.x; j < L; j += blockDim.x) sdst[j] = W.sp[j];
     if (plan.h_in_lds)
-        for (int e = threadIdx.x; e < q * L; e += blockDim.x) hdst[e] = W.h[e];
+        for (int e = threadIdx.x; e < (q - 1) * L; e += blockDim.x) hdst[e] = W.h[e];
     if (threadIdx.x < kQMax) P.counts[w * kQMax + threadIdx.x] = W.cnt[threadIdx.x];
 }
 
@@ -232,8 +232,9 @@ __device__ __forceinline__ void store_walker(const Inst &P, const Walker<F> &W, 
 // Field table from the spins, FP64 accumulation (exact for int tables).  For
 // each state k a bitmask per 64-site block lists the sites in state k; every
 // thread owns sites j and walks the set bits (wave-uniform, scalar), adding
-// the coupling to j.  The energy E = -1/2 sum_j h[s_j][j] (real units) is
-// formed from the FP64 sums.
+// the coupling to j.  Rows 0 .. q-2 are stored (row q-1 is implicit).  The
+// energy E = -1/2 sum_j h[s_j][j] (real units) is formed from the FP64 sums of
+// every row.
 // ---------------------------------------------------------------------------
 template <typename F>
 __device__ __forceinline__ double refresh_fields(const Inst &P, Walker<F> &W)
@@ -284,7 +285,7 @@ __device__ __forceinline__ double refresh_fields(const Inst &P, Walker<F> &W)
                 }
             }
             if (ok) {
-                W.h[k * L + j] = static_cast<F>(acc);
+                if (k < q - 1) W.h[k * L + j] = static_cast<F>(acc);  // row q-1 is implicit
                 if (k == sj) epart += acc;
             }
         }
@@ -736,13 +737,62 @@ __device__ __forceinline__ void add_flips_wg(const Walker<F> &W, int L, int i, i
     ex += 2;
 }
 
+// Field of state c at site i from the table (table units, in FP64): rows
+// 0 .. q-2 are stored, row q-1 is the coupling sum of the table's couplings
+// minus the others (the q fields of a site sum to it).
+template <typename F>
+__device__ __forceinline__ double tab_entry(const Inst &P, const Walker<F> &W, int c, int i)
+{
+    const int L = P.L, r = P.q - 1;
+    if (c < r) return static_cast<double>(W.h[c * L + i]);
+    double v = P.hsum;
+    for (int k = 0; k < r; ++k) v -= static_cast<double>(W.h[k * L + i]);
+    return v;
+}
+
+// h[a][i] - h[b][i] from the table.  Up to eight stored rows (q <= 9) every
+// lane reads them all at once (independent loads, in flight together: the
+// table may be in HBM) and picks its two entries, with no divergent branch in
+// the chain's serial path.
+template <typename F>
+__device__ __forceinline__ double tab_dE(const Inst &P, const Walker<F> &W, int a, int b, int i)
+{
+    const int L = P.L, r = P.q - 1;
+    if (r <= 3) {  // the short form: three loads, four selects
+        const double v0 = static_cast<double>(W.h[i]);
+        const double v1 = r > 1 ? static_cast<double>(W.h[L + i]) : 0.0;
+        const double v2 = r > 2 ? static_cast<double>(W.h[2 * L + i]) : 0.0;
+        const double last = ((P.hsum - v0) - v1) - v2;  // subtracting the zeros is exact
+        const double ha = a == r ? last : (a == 0 ? v0 : (a == 1 ? v1 : v2));
+        const double hb = b == r ? last : (b == 0 ? v0 : (b == 1 ? v1 : v2));
+        return ha - hb;
+    }
+    if (r <= 8) {
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = k < r ? static_cast<double>(W.h[k * L + i]) : 0.0;
+        double last = P.hsum;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) last -= v[k];  // subtracting the zeros is exact
+        double ha = last, hb = last;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            ha = a == k && k < r ? v[k] : ha;
+            hb = b == k && k < r ? v[k] : hb;
+        }
+        return ha - hb;
+    }
+    return tab_entry(P, W, a, i) - tab_entry(P, W, b, i);
+}
+
 // dE = h[a][i] - h[b][i] as the chain sees it: the two table entries (window
 // start) plus the window's flips 0..np-1 (all earlier than any live lane).
 template <typename F, bool D>
-__device__ __forceinline__ double dE_now(const Walker<F> &W, int L, int a, int b, int i, int np, int &ex, int &pbuf)
+__device__ __forceinline__ double dE_now(const Inst &P, const Walker<F> &W, int L, int a, int b, int i, int np, int &ex,
+                                         int &pbuf)
 {
     const int lane = threadIdx.x & (kWave - 1);
-    double dE = static_cast<double>(W.h[a * L + i]) - static_cast<double>(W.h[b * L + i]);
+    double dE = tab_dE(P, W, a, b, i);
     const uint32_t pv = lane < np ? W.pend[lane] : kNoFlip;
     ex = 0;
     add_flips_wg<F, D>(W, L, i, kWave, state_code(a, b), pv, 0, np, dE, ex, pbuf);
@@ -854,12 +904,12 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
         dE = sel4(snap->v, a) - sel4(snap->v, b);
         add_flips_wg<F, D, false, GRP>(W, L, i, kWave, state_code(a, b), snap->prev, 0, snap->nprev, dE, ex, pbuf);
     } else {
-        dE = static_cast<double>(W.h[a * L + i]) - static_cast<double>(W.h[b * L + i]);
+        dE = tab_dE(P, W, a, b, i);
     }
     uint32_t code = state_code(a, b);
     uint64_t live = ballot(valid);
     int np = 0;
-    double Bd = 2.0 * (P.bound_init + static_cast<double>(cr.nupd) * P.bound_unit);
+    double Bd = P.bound_rows * (P.bound_init + static_cast<double>(cr.nupd) * P.bound_unit) + P.bound_impl;
     const double dBd = 2.0 * P.bound_unit;
     const double tfix = kBand + kEvalMargin;
     // dE, its bounds and eL are in table units (real value = qscale * units; the
@@ -1005,7 +1055,7 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
                 const uint32_t pv = lane < np ? W.pend[lane] : kNoFlip;
                 add_flips_wg<F, D, false, GRP>(W, L, i, kWave, state_code(a2, bb), pv, 0, np, dE2, ex2, pbuf);
             } else {
-                dE2 = dE_now<F, D>(W, L, redo ? sn : a, redo ? b2 : b, i, np, ex2, pbuf);
+                dE2 = dE_now<F, D>(P, W, L, redo ? sn : a, redo ? b2 : b, i, np, ex2, pbuf);
             }
             if (redo) {
                 a = sn;
@@ -1046,7 +1096,8 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
 // ones); its error against the exact change is at most the bound_flipE the
 // caller charges per flip.
 template <typename F, int QT, bool D>
-__device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np, double &part, int tid, int NT)
+__device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np, double &part, int tid, int NT,
+                                             int nrows)
 {
     constexpr int QR = QT > 0 ? QT : 1;  // rows held in registers (q <= QT)
     constexpr int M = kFlushM;             // register slots per thread
@@ -1063,6 +1114,7 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
         const uint32_t mine = lane < np ? ((1u << fw_old(pv)) | (1u << fw_new(pv))) : 0u;
 #pragma unroll
         for (int c = 0; c < QT; ++c) touched |= ballot((mine >> c) & 1u) ? (1u << c) : 0u;
+        touched &= (1u << nrows) - 1u;  // rows the table stores
     }
     for (int jb = (tid / kWave) * kWave * M; jb < L; jb += NT * M) {
         const int j0 = jb + lane;
@@ -1092,100 +1144,110 @@ __device__ __forceinline__ void flush_window(const Inst &P, Walker<F> &W, int np
                 hr[c][m] = (((touched >> c) & 1u) && ok[m]) ? static_cast<RT>(W.h[c * L + jm[m]]) : RT(0);
         (void)hr;
         const F *Jrow = W.J + (j0 + L);  // D: coupling of site j0 + 64 m to site ip is Jrow[64 m - ip]
-        for (int p0 = 0; p0 < np; p0 += B) {
-            uint32_t pkb[B];
-            RT g[B][M];
-#pragma unroll
-            for (int e = 0; e < B; ++e) {
-                // p0 + e <= 63; lanes past np hold the no-flip word
-                pkb[e] = static_cast<uint32_t>(rl_i(static_cast<int>(pv), p0 + e));
-                const int ip = fw_site(pkb[e]);
-#pragma unroll
-                for (int m = 0; m < M; ++m) {
-                    if constexpr (D) {
-                        g[e][m] = static_cast<RT>(Jrow[m * kWave - ip]);
-                    } else {
-                        int d = jm[m] - ip;
-                        d += d < 0 ? L : 0;
-                        g[e][m] = static_cast<RT>(W.J[d]);
-                    }
-                }
-            }
-            // no branch per flip: padding entries have all coefficients 0
-            if constexpr (QT == 4 && !kI32) {
+        // the batches of the window's flips; kTab: coefficient rows from the
+        // LDS table (the two- and four-row forms run only for q <= 4, every
+        // state below 4), else computed from the flip's states
+        auto batches = [&](auto tab) {
+            constexpr bool kTab = decltype(tab)::value;
+            for (int p0 = 0; p0 < np; p0 += B) {
+                uint32_t pkb[B];
+                RT g[B][M];
 #pragma unroll
                 for (int e = 0; e < B; ++e) {
-                    const F *kc = W.ctab + ((pkb[e] >> 16) & 0x3Fu) * 4;  // one broadcast row per flip
-#pragma unroll
-                    for (int c = 0; c < QT; ++c) {
-                        const F k = kc[c];
-#pragma unroll
-                        for (int m = 0; m < M; ++m)
-                            hr[c][m] = fma(k, g[e][m], hr[c][m]);
-                    }
-                }
-            } else if constexpr (QT > 0) {
-                // every row, flip by flip (no branch: QT * M independent fma per flip)
-#pragma unroll
-                for (int e = 0; e < B; ++e) {
-                    const int ap = fw_old(pkb[e]), bp = fw_new(pkb[e]);
-#pragma unroll
-                    for (int c = 0; c < QT; ++c) {
-                        const RT k = flip_coef<RT>(c, ap, bp);  // wave-uniform; padding: 0
-#pragma unroll
-                        for (int m = 0; m < M; ++m) hr[c][m] = fma(k, g[e][m], hr[c][m]);
-                    }
-                }
-            }
-            if (kF32) {
-#pragma unroll
-                for (int e = 0; e < B; ++e) {
-                    const bool real = p0 + e < np;
-                    const int ip = fw_site(pkb[e]), ap = fw_old(pkb[e]), bp = fw_new(pkb[e]);
+                    // p0 + e <= 63; lanes past np hold the no-flip word
+                    pkb[e] = static_cast<uint32_t>(rl_i(static_cast<int>(pv), p0 + e));
+                    const int ip = fw_site(pkb[e]);
 #pragma unroll
                     for (int m = 0; m < M; ++m) {
-                        const int sj = sr[m];
-                        const double gv = static_cast<double>(g[e][m]);
-                        part += (real && sj == ap) ? gv : ((real && sj == bp) ? -gv : 0.0);
-                        sr[m] = (real && ok[m] && jm[m] == ip) ? bp : sj;
+                        if constexpr (D) {
+                            g[e][m] = static_cast<RT>(Jrow[m * kWave - ip]);
+                        } else {
+                            int d = jm[m] - ip;
+                            d += d < 0 ? L : 0;
+                            g[e][m] = static_cast<RT>(W.J[d]);
+                        }
                     }
                 }
-            }
-            if constexpr (QT == 0) {
-                // larger q: the rows this batch touches, one after another; each
-                // entry is read once, takes the batch's flips in order and is
-                // written once, and the next row's read is issued before this
-                // row's write (no write-to-read wait; the table may be in HBM)
-                uint32_t rows = 0;
-#pragma unroll
-                for (int e = 0; e < B; ++e) rows |= (1u << fw_old(pkb[e])) | (1u << fw_new(pkb[e]));
-                int c = static_cast<int>(__builtin_ctz(rows));  // rows != 0: padding touches row 0
-                RT vn[M];
-#pragma unroll
-                for (int m = 0; m < M; ++m) vn[m] = ok[m] ? static_cast<RT>(W.h[c * L + jm[m]]) : RT(0);
-                while (c >= 0) {
-                    RT v[M];
-#pragma unroll
-                    for (int m = 0; m < M; ++m) v[m] = vn[m];
-                    rows &= rows - 1u;
-                    const int cn = rows ? static_cast<int>(__builtin_ctz(rows)) : -1;
-                    if (cn >= 0) {
-#pragma unroll
-                        for (int m = 0; m < M; ++m) vn[m] = ok[m] ? static_cast<RT>(W.h[cn * L + jm[m]]) : RT(0);
-                    }
+                // no branch per flip: padding entries have all coefficients 0
+                if constexpr (kTab) {
 #pragma unroll
                     for (int e = 0; e < B; ++e) {
-                        const RT k = flip_coef<RT>(c, fw_old(pkb[e]), fw_new(pkb[e]));  // padding: 0
+                        const F *kc = W.ctab + ((pkb[e] >> 16) & 0x3Fu) * 4;  // one broadcast row per flip
 #pragma unroll
-                        for (int m = 0; m < M; ++m) v[m] = fma(k, g[e][m], v[m]);
+                        for (int c = 0; c < QT; ++c) {
+                            const F k = kc[c];
+#pragma unroll
+                            for (int m = 0; m < M; ++m)
+                                hr[c][m] = fma(k, g[e][m], hr[c][m]);
+                        }
                     }
+                } else if constexpr (QT > 0) {
+                    // every row, flip by flip (no branch: QT * M independent fma per flip)
 #pragma unroll
-                    for (int m = 0; m < M; ++m)
-                        if (ok[m]) W.h[c * L + jm[m]] = static_cast<F>(v[m]);
-                    c = cn;
+                    for (int e = 0; e < B; ++e) {
+                        const int ap = fw_old(pkb[e]), bp = fw_new(pkb[e]);
+#pragma unroll
+                        for (int c = 0; c < QT; ++c) {
+                            const RT k = flip_coef<RT>(c, ap, bp);  // wave-uniform; padding: 0
+#pragma unroll
+                            for (int m = 0; m < M; ++m) hr[c][m] = fma(k, g[e][m], hr[c][m]);
+                        }
+                    }
+                }
+                if (kF32) {
+#pragma unroll
+                    for (int e = 0; e < B; ++e) {
+                        const bool real = p0 + e < np;
+                        const int ip = fw_site(pkb[e]), ap = fw_old(pkb[e]), bp = fw_new(pkb[e]);
+#pragma unroll
+                        for (int m = 0; m < M; ++m) {
+                            const int sj = sr[m];
+                            const double gv = static_cast<double>(g[e][m]);
+                            part += (real && sj == ap) ? gv : ((real && sj == bp) ? -gv : 0.0);
+                            sr[m] = (real && ok[m] && jm[m] == ip) ? bp : sj;
+                        }
+                    }
+                }
+                if constexpr (QT == 0) {
+                    // larger q: the rows this batch touches, one after another; each
+                    // entry is read once, takes the batch's flips in order and is
+                    // written once, and the next row's read is issued before this
+                    // row's write (no write-to-read wait; the table may be in HBM)
+                    uint32_t rows = 0;
+#pragma unroll
+                    for (int e = 0; e < B; ++e) rows |= (1u << fw_old(pkb[e])) | (1u << fw_new(pkb[e]));
+                    // stored rows only; rows != 0: a flip touches two states, at
+                    // most one of them the implicit last, and padding touches row 0
+                    rows &= (1u << nrows) - 1u;
+                    int c = static_cast<int>(__builtin_ctz(rows));
+                    RT vn[M];
+#pragma unroll
+                    for (int m = 0; m < M; ++m) vn[m] = ok[m] ? static_cast<RT>(W.h[c * L + jm[m]]) : RT(0);
+                    while (c >= 0) {
+                        RT v[M];
+#pragma unroll
+                        for (int m = 0; m < M; ++m) v[m] = vn[m];
+                        rows &= rows - 1u;
+                        const int cn = rows ? static_cast<int>(__builtin_ctz(rows)) : -1;
+                        if (cn >= 0) {
+#pragma unroll
+                            for (int m = 0; m < M; ++m) vn[m] = ok[m] ? static_cast<RT>(W.h[cn * L + jm[m]]) : RT(0);
+                        }
+#pragma unroll
+                        for (int e = 0; e < B; ++e) {
+                            const RT k = flip_coef<RT>(c, fw_old(pkb[e]), fw_new(pkb[e]));  // padding: 0
+#pragma unroll
+                            for (int m = 0; m < M; ++m) v[m] = fma(k, g[e][m], v[m]);
+                        }
+#pragma unroll
+                        for (int m = 0; m < M; ++m)
+                            if (ok[m]) W.h[c * L + jm[m]] = static_cast<F>(v[m]);
+                        c = cn;
+                    }
                 }
             }
-        }
+        };
+        batches(std::integral_constant<bool, (QT == 4 || QT == 2) && !kI32>{});
 #pragma unroll
         for (int c = 0; c < QT; ++c)
 #pragma unroll
@@ -1219,7 +1281,7 @@ __device__ __forceinline__ double sweep_walker(const Inst &P, Walker<F> &W, int 
             ph_mark(ph, kPhChain);
             const int np = W.cs->np[(t0 / kWave) & 1];
             if (TAB && np > 0) {  // without a table the chain works from direct sums: nothing to flush
-                flush_window<F, QT, D>(P, W, np, part, threadIdx.x, blockDim.x);
+                flush_window<F, QT, D>(P, W, np, part, threadIdx.x, blockDim.x, P.q - 1);
                 __syncthreads();
                 ph_mark(ph, kPhFlush);
                 if (ph.on) ++ph.v[kPhFlushes];
@@ -1268,8 +1330,14 @@ __device__ __forceinline__ double sweep_walker_ov(const Inst &P, Walker<F> &W, i
         if (chainw && s < nwin) {
             const int ta = t0 + lane;
             const int i = ta < L ? static_cast<int>(W.draw[ta] & 0xFFFFu) : 0;
+            double last = P.hsum;  // row q-1: the coupling sum minus the stored rows
 #pragma unroll
-            for (int c = 0; c < 4; ++c) sn.v[c] = c < q ? static_cast<double>(W.h[c * L + i]) : 0.0;
+            for (int c = 0; c < 4; ++c) {
+                sn.v[c] = c < q - 1 ? static_cast<double>(W.h[c * L + i]) : 0.0;
+                last -= sn.v[c];
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) sn.v[c] = c == q - 1 ? last : sn.v[c];
         }
         __syncthreads();  // the snapshot is read before the flush below writes the table
         if (chainw) {
@@ -1281,7 +1349,7 @@ __device__ __forceinline__ double sweep_walker_ov(const Inst &P, Walker<F> &W, i
             if (ph.on) ph.t = clock64();
             Walker<F> Wf = W;
             Wf.pend = pend0 + ((s - 1) & 1) * kWave;
-            flush_window<F, QT, true>(P, Wf, np_prev, part, threadIdx.x - nc * kWave, nc * kWave);
+            flush_window<F, QT, true>(P, Wf, np_prev, part, threadIdx.x - nc * kWave, nc * kWave, P.q - 1);
             ph_mark(ph, kPhFlush);
             if (ph.on) ++ph.v[kPhFlushes];
         }
@@ -1331,11 +1399,12 @@ __device__ __forceinline__ void record_sweep(const Inst &P, const Walker<F> &W, 
 // a fixed order (lane-strided partial sums, then the butterfly reduction, which
 // leaves the same value in every lane), so that every caller gets the same
 // bits whatever its workgroup size.
-__device__ __forceinline__ double coupling_sum_wave(const double *J64, int L)
+template <typename T>
+__device__ __forceinline__ double coupling_sum_wave(const T *J, int L)
 {
     const int lane = threadIdx.x & (kWave - 1);
     double part = 0.0;
-    for (int r = 1 + lane; r < L; r += kWave) part += J64[r];
+    for (int r = 1 + lane; r < L; r += kWave) part += static_cast<double>(J[r]);
     return wave_sum(part);
 }
 
@@ -1352,7 +1421,8 @@ __device__ __forceinline__ double coupling_error_wave(const double *J64, const T
 // After the couplings J64/J32 are written (the whole workgroup, at least one
 // wave): the quantised couplings Jq(r) = rint(J*(r) 2^k), k the largest with
 // S 2^k + L < 2^31 - 2 (no field of an int table can then overflow), and the
-// table bounds at P.bnd for precision prec (lane 0 of wave 0 writes them).
+// table bounds at P.bnd for precision prec (lane 0 of wave 0 writes them),
+// with the coupling sum of the table's own couplings (its implicit row).
 __device__ void setup_couplings(const Inst &P, int prec)
 {
     __shared__ double s_scale;
@@ -1374,7 +1444,10 @@ __device__ void setup_couplings(const Inst &P, int prec)
     if (threadIdx.x < kWave) {
         const double D32 = coupling_error_wave(P.J64, P.J32, 1.0, L);
         const double Dq = coupling_error_wave(P.J64, P.Jq, 1.0 / up, L);
-        if (threadIdx.x == 0) *P.bnd = table_bounds(S, P.J64[1], D32, Dq, L, prec, 1.0 / up);
+        // int sums are exact (|sum| < 2^31); FP32 couplings are summed in FP64
+        const double Stab = prec == kPrecI32 ? coupling_sum_wave(P.Jq, L)
+                                             : (prec == kPrecF32 ? coupling_sum_wave(P.J32, L) : S);
+        if (threadIdx.x == 0) *P.bnd = table_bounds(S, P.J64[1], D32, Dq, L, prec, 1.0 / up, P.q, Stab);
     }
     __syncthreads();
 }

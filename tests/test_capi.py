@@ -45,7 +45,7 @@ def test_host_only_calls():
     assert opt.precision == pkg.PREC_F64 and opt.init == pkg.INIT_RANDOM
     n = ctypes.c_size_t(0)
     assert lib.pt_workspace_size(1024, 3, 64, ctypes.byref(opt), ctypes.byref(n)) == 0
-    assert n.value > 1024 * 3 * 64 * 8
+    assert n.value > 1024 * 2 * 64 * 8  # rows 0 and 1 of q = 3 (the last row is implicit)
     opt.precision = pkg.PREC_F32
     n32 = ctypes.c_size_t(0)
     assert lib.pt_workspace_size(1024, 3, 64, ctypes.byref(opt), ctypes.byref(n32)) == 0

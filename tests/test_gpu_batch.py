@@ -156,7 +156,7 @@ def test_server_admission_by_memory(pkg, orc):
 
     jobs = [dict(L=512, q=4, sigma=0.5, T=geometric_ladder(0.3, 3.0, 16), seed=900 + j, sweeps=8,
                  exchange_every=1, init=0) for j in range(4)]
-    one = 16 * 512 * 4 * 8 + 16 * 512 + (1 << 16)
+    one = 16 * 512 * 3 * 8 + 16 * 512 + (1 << 16)  # q - 1 stored rows, spins, the rest
     srv = pkg.Server(arena_bytes=one + (one // 2), max_jobs=8)
     try:
         ids = [srv.submit(j) for j in jobs]
