@@ -36,6 +36,19 @@ int ptmi_lds_read_bandwidth(int32_t blocks, int32_t threads, int32_t iters, doub
  * not fit in LDS), or another negative value if a HIP call failed. */
 int ptmi_flush_replay(int32_t L, int32_t q, const double *jstar, const double *h0, const uint32_t *words,
                       int64_t nwords, int32_t workgroups, int32_t reps, double *h_out, double *ms_out);
+/* Issue rate of one instruction kind (0: FP64 FMA, 1: FP32 FMA) at a given
+ * occupancy: `blocks` workgroups of `threads`
+ * threads (a multiple of 64, at most 1024), each thread updating 16
+ * independent accumulators `iters` times (at most 2^20) with multiplier 1 and
+ * addend 1, timed with HIP events on the null stream after a warm-up launch.
+ * *ms_out receives the timed launch; *sum_out the sum of thread 0's
+ * accumulators in workgroup 0, 120 + 16 iters exactly, which shows the
+ * instructions ran.  With one workgroup of 256 threads per CU there is one
+ * wave per SIMD: ms / (16 iters) is the time between two issues of the kind by
+ * one wave.  Returns 0, -1 on a bad argument, or another negative value if a
+ * HIP call failed. */
+int ptmi_valu_issue_rate(int32_t kind, int32_t blocks, int32_t threads, int32_t iters, double *ms_out,
+                         double *sum_out);
 #ifdef __cplusplus
 }
 #endif

@@ -70,7 +70,71 @@ __global__ __launch_bounds__(kReplayThreads) void k_flush_replay(int L, int q, i
         for (int e = threadIdx.x; e < q * L; e += blockDim.x) h_out[e] = hl[e];
 }
 
+// Issue rate of independent wave64 VALU instructions: every thread keeps 16
+// accumulators and updates each `iters` times with one FMA of the kind (0:
+// FP64, 1: FP32), with the multiplier 1 and the addend c from the host, so the
+// results are exact and known: thread 0 of workgroup 0 writes the sum of its
+// accumulators.
+template <int K>
+__global__ __launch_bounds__(1024) void k_valu(int iters, double bd, double cd, float bf, float cf, double *sum_out)
+{
+    double ad[16];
+    float af[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        ad[k] = k;
+        af[k] = static_cast<float>(k);
+    }
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            if constexpr (K == 0) ad[k] = fma(ad[k], bd, cd);
+            if constexpr (K == 1) af[k] = fmaf(af[k], bf, cf);
+        }
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) s += K == 0 ? ad[k] : static_cast<double>(af[k]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *sum_out = s;
+}
+
 }  // namespace
+
+extern "C" int ptmi_valu_issue_rate(int32_t kind, int32_t blocks, int32_t threads, int32_t iters, double *ms_out,
+                                    double *sum_out)
+{
+    if (kind < 0 || kind > 1 || blocks < 1 || threads < 64 || threads > 1024 || threads % 64 || iters < 1 ||
+        iters > (1 << 20) || !ms_out || !sum_out)
+        return -1;
+    double *dsum = nullptr;
+    if (hipMalloc(&dsum, sizeof(double)) != hipSuccess) return -3;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = 0;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = -5;
+    auto launch = [&](int n) {
+        if (kind == 0)
+            hipLaunchKernelGGL(k_valu<0>, dim3(blocks), dim3(threads), 0, 0, n, 1.0, 1.0, 1.0f, 1.0f, dsum);
+        else
+            hipLaunchKernelGGL(k_valu<1>, dim3(blocks), dim3(threads), 0, 0, n, 1.0, 1.0, 1.0f, 1.0f, dsum);
+    };
+    float ms = 0.f;
+    if (!rc) {
+        launch(16);  // warm-up
+        if (hipEventRecord(e0, 0) != hipSuccess) rc = -6;
+    }
+    if (!rc) {
+        launch(iters);
+        if (hipGetLastError() != hipSuccess || hipEventRecord(e1, 0) != hipSuccess ||
+            hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            rc = -6;
+    }
+    if (!rc && hipMemcpy(sum_out, dsum, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) rc = -7;
+    *ms_out = ms;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(dsum);
+    return rc;
+}
 
 extern "C" int ptmi_flush_replay(int32_t L, int32_t q, const double *jstar, const double *h0, const uint32_t *words,
                                  int64_t nwords, int32_t workgroups, int32_t reps, double *h_out, double *ms_out)

@@ -42,6 +42,8 @@ def probe():
         lib.ptmi_lds_read_bandwidth.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                                 ctypes.POINTER(ctypes.c_double)]
         lib.ptmi_lds_read_bandwidth.restype = ctypes.c_int
+        lib.ptmi_valu_issue_rate.argtypes = [ctypes.c_int32] * 4 + [ctypes.POINTER(ctypes.c_double)] * 2
+        lib.ptmi_valu_issue_rate.restype = ctypes.c_int
         _probe = lib
     return _probe
 
@@ -82,6 +84,21 @@ def lds_peak():
     return bw.value
 
 
+VALU_KINDS = ("fp64_fma", "fp32_fma")
+
+
+def valu_issue(kind, threads, iters=20000, blocks=256):
+    """Time between two issues of one VALU instruction kind by one wave, in ns,
+    with threads/64 waves per CU (one workgroup per CU: `blocks` = the CU
+    count), and the checksum the probe returns (120 + 16 iters)."""
+    ms, s = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    rc = probe().ptmi_valu_issue_rate(VALU_KINDS.index(kind), blocks, threads, iters, ctypes.byref(ms), ctypes.byref(s))
+    if rc != 0:
+        raise RuntimeError(f"ptmi_valu_issue_rate failed ({rc})")
+    waves_per_simd = max(1, threads // 256)
+    return ms.value * 1e6 / (16.0 * iters * waves_per_simd), s.value
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--L", type=int, default=1024)
@@ -110,8 +127,11 @@ def main(argv=None):
         runs.append({"workgroups": wg, "ms": round(ms, 3), "flips_per_s": flips / (ms * 1e-3),
                      "lds_GBps": rate / 1e9, "frac_of_peak": rate / peak,
                      "frac_of_occupied_cus": rate / (peak * min(wg, 256) / 256)})
+    # the time per issue of one VALU kind by a wave at one and at two waves per SIMD
+    issue = {f"{k}_ns_{t // 256}w": round(valu_issue(k, t)[0], 4) for k in VALU_KINDS for t in (256, 512)}
     print(json.dumps({"L": a.L, "q": a.q, "flips": a.flips, "reps": a.reps, "max_abs_err_vs_fields": err,
-                      "lds_peak_GBps": peak / 1e9, "bytes_per_flip": 40 * a.L, "runs": runs}))
+                      "lds_peak_GBps": peak / 1e9, "bytes_per_flip": 40 * a.L, "runs": runs,
+                      "valu_issue": issue}))
 
 
 if __name__ == "__main__":

@@ -1,7 +1,8 @@
 """The field update alone (the sweep kernel's flush, through the probe
 library's C entry point): after a flip sequence the FP64 table must equal the
 fields recomputed from the final spins, h[k][j] = sum_{i != j} J*(|i-j|)
-[s_i = k], to the rounding of the updates; bad words are refused on the host."""
+[s_i = k], to the rounding of the updates; bad words are refused on the host.
+The VALU issue-rate probe beside it runs every instruction it times."""
 import numpy as np
 import pytest
 
@@ -56,3 +57,23 @@ def test_replay_refuses_bad_words(fb, orc):
         fb.replay(J, 3, np.array([64], np.uint32), workgroups=1, reps=1)  # site 64 of 64
     with pytest.raises(RuntimeError):
         fb.replay(J, 3, np.array([5 | (3 << 20)], np.uint32), workgroups=1, reps=1)  # state 3 of q = 3
+
+
+@pytest.mark.parametrize("kind", ["fp64_fma", "fp32_fma"])
+@pytest.mark.parametrize("threads", [256, 512])
+def test_valu_issue_probe_runs_every_instruction(fb, kind, threads):
+    """The issue-rate probe's checksum: 16 accumulators starting at 0..15, each
+    updated iters times by x * 1 + 1, sum to 120 + 16 iters exactly."""
+    ns, total = fb.valu_issue(kind, threads, iters=4096, blocks=8)
+    assert total == 120 + 16 * 4096
+    assert ns > 0.0
+
+
+def test_valu_issue_probe_refuses_bad_arguments(fb):
+    import ctypes
+
+    ms, s = ctypes.c_double(), ctypes.c_double()
+    lib = fb.probe()
+    assert lib.ptmi_valu_issue_rate(2, 1, 256, 10, ctypes.byref(ms), ctypes.byref(s)) == -1  # no such kind
+    assert lib.ptmi_valu_issue_rate(0, 1, 100, 10, ctypes.byref(ms), ctypes.byref(s)) == -1  # not whole waves
+    assert lib.ptmi_valu_issue_rate(0, 1, 256, (1 << 20) + 1, ctypes.byref(ms), ctypes.byref(s)) == -1
