@@ -102,7 +102,11 @@ def phase_summary(ph, inst, prec, placement):
            "hottest_walker": {"walker": hot, "flips": int(ph["flips"][hot]),
                               "cycles_share": {k: float(ph[k][hot] / tot[hot])
                                                for k in ("draw", "chain", "flush", "record", "exchange")},
-                              "iters_per_window": float(ph["iters"][hot] / max(1, ph["windows"][hot]))}}
+                              "iters_per_window": float(ph["iters"][hot] / max(1, ph["windows"][hot])),
+                              # the chain's cycles by step of its guess-and-check iterations
+                              "chain_split": {k[6:]: float(ph[k][hot] / max(1, ph["chain"][hot]))
+                                              for k in ("chain_guess", "chain_correct", "chain_check",
+                                                        "chain_resolve", "chain_redo", "chain_sync")}}}
     if placement != 3 and ph["flush"].sum() > 0:
         # algorithmic field-update bytes (5 f L per flip) per flush cycle of each
         # walker's workgroup, i.e. per CU, against 256 B/clk/CU

@@ -196,7 +196,14 @@ enum {
     PT_PHASE_FLUSHES = 7,   /* count: windows with flips to apply                      */
     PT_PHASE_FLIPS = 8,     /* count: accepted flips                                   */
     PT_PHASE_ITERS = 9,     /* count: guess-and-check iterations of the chain          */
-    PT_PHASE_N = 10
+    /* the chain's cycles by step of its iterations (single instances; part of CHAIN): */
+    PT_PHASE_CHAIN_GUESS = 10,    /* sure accepts guessed, same-site cut, compaction   */
+    PT_PHASE_CHAIN_CORRECT = 11,  /* guessed flips applied to the later lanes' dE      */
+    PT_PHASE_CHAIN_CHECK = 12,    /* re-decisions, commits, counters                   */
+    PT_PHASE_CHAIN_RESOLVE = 13,  /* first differing lane decided, later lanes rebuilt */
+    PT_PHASE_CHAIN_REDO = 14,     /* lanes whose site changed: dE re-derived           */
+    PT_PHASE_CHAIN_SYNC = 15,     /* workgroup barrier closing an iteration            */
+    PT_PHASE_N = 16
 };
 pt_status pt_get_phase_counters(pt_ctx *ctx, uint64_t *out);
 

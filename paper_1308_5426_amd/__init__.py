@@ -24,7 +24,8 @@ PT_OK, PT_EINVAL, PT_ENOMEM, PT_EDEVICE, PT_ESTATE = 0, -1, -2, -3, -4
 PREC_F64, PREC_F32, PREC_I32 = 0, 1, 2
 INIT_RANDOM, INIT_ORDERED = 0, 1
 PLACE_AUTO, PLACE_LDS, PLACE_HBM, PLACE_DIRECT = 0, 1, 2, 3
-PHASES = ("draw", "chain", "flush", "record", "exchange", "total", "windows", "flushes", "flips", "iters")
+PHASES = ("draw", "chain", "flush", "record", "exchange", "total", "windows", "flushes", "flips", "iters",
+          "chain_guess", "chain_correct", "chain_check", "chain_resolve", "chain_redo", "chain_sync")
 QMAX = 16
 BAND = 1e-9
 

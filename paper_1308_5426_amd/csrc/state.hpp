@@ -37,7 +37,14 @@ enum Phase : int {
     kPhFlushes = 7,     // windows with at least one flip to apply
     kPhFlips = 8,       // accepted flips
     kPhIters = 9,       // guess-and-check iterations of the chain
-    kPhN = 10
+    // the chain's cycles by step of its iterations (part of kPhChain):
+    kPhCGuess = 10,     // the guess: sure accepts, same-site cut, compaction
+    kPhCCorr = 11,      // the guessed flips applied to later lanes' dE
+    kPhCCheck = 12,     // re-decisions, commits and counters
+    kPhCResolve = 13,   // the first differing lane decided, later lanes rebuilt
+    kPhCRedo = 14,      // lanes whose site an earlier flip changed, dE re-derived
+    kPhCSync = 15,      // the workgroup barrier closing an iteration
+    kPhN = 16
 };
 
 // Table precisions (values of PT_PREC_*).

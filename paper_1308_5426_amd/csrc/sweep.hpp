@@ -877,8 +877,19 @@ __device__ __forceinline__ double direct_dE_window(const Walker<F> &W, int L, in
 // more such units per lane.
 template <typename F, bool D, bool DIR, bool GRP = false>
 __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w, int64_t n, double beta_r, int t0,
-                                             int c0, int cend, ChainRegs &cr, int &pbuf, const Snap *snap = nullptr)
+                                             int c0, int cend, ChainRegs &cr, int &pbuf, const Snap *snap = nullptr,
+                                             PhaseAcc *php = nullptr)
 {
+    // profiled runs: thread 0 charges each step of an iteration to its counter
+    const bool pon = php && php->on;
+    uint64_t tq = pon ? clock64() : 0;
+    auto mark = [&](int k) {
+        if (pon) {
+            const uint64_t t = clock64();
+            php->v[k] += t - tq;
+            tq = t;
+        }
+    };
     constexpr bool kF64 = sizeof(F) == sizeof(double);
     constexpr bool kI32 = table_prec<F>() == kPrecI32;
     const int L = P.L, q = P.q, lane = threadIdx.x & (kWave - 1);
@@ -943,7 +954,9 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
         const double dE0 = dE;
         const int ex0 = ex;
         const uint32_t lst = compact_flips(S, lane, pk);  // lane r: the r-th guessed flip
+        mark(kPhCGuess);
         add_flips_wg<F, D, false, GRP>(W, L, i, lane, code, lst, 0, __popcll(S), dE, ex, pbuf);
+        mark(kPhCCorr);
         // check: each lane decides with the guessed flips before it
         const double x = beta * dE + lnu;
         const int r = __popcll(S & mine_below);
@@ -971,6 +984,7 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
         if (!DIR) cr.nupd += nc;  // flips the table will take (none without a table)
         cr.nacc += nc;
         Bd += static_cast<double>(nc) * dBd;
+        mark(kPhCCheck);
         if (V) {
             // lane m holds exactly the committed flips: decide it
             const uint32_t pk_m = static_cast<uint32_t>(rl_i(static_cast<int>(pk), m));
@@ -1030,6 +1044,7 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
         } else {
             live &= ~lanes_below(hz);
         }
+        mark(kPhCResolve);
         // a later lane whose site's spin changed: new current state, dE re-derived
         const int sn = W.sp[i];
         const bool redo = ((live >> lane) & 1ull) && sn != a;
@@ -1065,9 +1080,11 @@ __device__ __forceinline__ void chain_window(const Inst &P, Walker<F> &W, int w,
                 ex = ex2;
             }
         }
+        mark(kPhCRedo);
         // every wave has finished reading this iteration's spins before any
         // wave writes the next iteration's commits
         if (chain_nw<GRP>() > 1) chain_sync<GRP>(W);
+        mark(kPhCSync);
     }
     if (lead && lane == 0) W.cs->np[(t0 / kWave) & 1] = np;
 }
@@ -1276,7 +1293,7 @@ __device__ __forceinline__ double sweep_walker(const Inst &P, Walker<F> &W, int 
         __syncthreads();
         ph_mark(ph, kPhDraw);
         for (int t0 = c0; t0 < cend; t0 += kWave) {
-            chain_window<F, D, !TAB>(P, W, w, n, beta, t0, c0, cend, cr, pbuf);
+            chain_window<F, D, !TAB>(P, W, w, n, beta, t0, c0, cend, cr, pbuf, nullptr, &ph);
             __syncthreads();
             ph_mark(ph, kPhChain);
             const int np = W.cs->np[(t0 / kWave) & 1];

@@ -139,6 +139,11 @@ def test_phase_counters(pkg, orc):
     timed = sum(ph[k] for k in ("draw", "chain", "flush", "record", "exchange"))
     assert (timed <= ph["total"]).all() and (timed >= 0.5 * ph["total"]).all()
     assert (ph["chain"] > 0).all()
+    # the chain's steps are timed inside its own phase, every one at least once
+    steps = [ph[k] for k in ("chain_guess", "chain_correct", "chain_check", "chain_resolve", "chain_redo",
+                             "chain_sync")]
+    assert (sum(steps) <= ph["chain"]).all()
+    assert all((x > 0).all() for x in steps[:3])
     plain = pkg.Simulation(L, 3, 0.5, T, 4)
     with pytest.raises(pkg.PTError):
         plain.phase_counters()
