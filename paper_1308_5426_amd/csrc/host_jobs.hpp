@@ -142,7 +142,8 @@ struct pt_batch {
     unsigned char *ws = nullptr;
     size_t ws_bytes = 0;
     bool own_ws = false, ran = false;
-    std::vector<JobSlot> slots;
+    std::vector<JobSlot> slots;       // by job index
+    std::vector<JobSlot> exec_slots;  // in launch order (the device's job table)
     std::vector<pt_job_desc> jobs;
     JobSlot *d_slots = nullptr;
     JobControl *d_ctl = nullptr;
@@ -248,19 +249,38 @@ pt_status pt_batch_create(pt_batch **out, const pt_job_desc *jobs, int32_t njobs
     b->d_T = reinterpret_cast<double *>(b->ws + b->T_off);
     b->slots.resize(njobs);
     b->jobs.assign(jobs, jobs + njobs);
+    // Launch order: the costliest jobs first (tickets go out job by job, so a
+    // large job taken last would run alone at the end of the launch).  Cost
+    // estimate: attempts, times L / 256 more for direct sums (each attempt an
+    // O(L) sum).  Each job's trajectory does not depend on the order.
+    std::vector<LdsPlan> plans(njobs);
+    std::vector<int32_t> variants(njobs);
+    std::vector<double> cost(njobs);
+    for (int j = 0; j < njobs; ++j) {
+        if ((st = job_plan(jobs[j], b->prec, b->budget, b->threads, &plans[j], &variants[j])) != PT_OK) return bail(st);
+        const double att = static_cast<double>(jobs[j].L) * jobs[j].R * static_cast<double>(jobs[j].sweeps);
+        cost[j] = plans[j].place == kPlDirect ? att * (1.0 + jobs[j].L / 256.0) : att;
+    }
+    std::vector<int32_t> order(njobs);
+    for (int j = 0; j < njobs; ++j) order[j] = j;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return cost[x] > cost[y]; });
     int32_t wbase = 0, maxR = 0;
     size_t toff = 0;
+    std::vector<size_t> T_at(njobs);
     for (int j = 0; j < njobs; ++j) {
-        LdsPlan plan;
-        int32_t variant = 0;
-        if ((st = job_plan(jobs[j], b->prec, b->budget, b->threads, &plan, &variant)) != PT_OK) return bail(st);
+        T_at[j] = toff;
         b->Tall.insert(b->Tall.end(), jobs[j].T, jobs[j].T + jobs[j].R);
-        job_slot(b->slots[j], jobs[j], b->prec, b->ws + b->job_off[j], b->d_T + toff, plan, variant, wbase,
-                 b->d_jc + 2 * static_cast<size_t>(j));
-        b->jobs[j].T = nullptr;
         toff += jobs[j].R;
-        wbase += jobs[j].R;
+        b->jobs[j].T = nullptr;
         maxR = std::max(maxR, jobs[j].R);
+    }
+    b->exec_slots.resize(njobs);
+    for (int k = 0; k < njobs; ++k) {
+        const int j = order[k];
+        job_slot(b->slots[j], jobs[j], b->prec, b->ws + b->job_off[j], b->d_T + T_at[j], plans[j], variants[j], wbase,
+                 b->d_jc + 2 * static_cast<size_t>(j));
+        b->exec_slots[k] = b->slots[j];
+        wbase += jobs[j].R;
     }
     int cap = 0;
     if ((st = jobs_capacity(b->prec, b->threads, b->budget, &cap)) != PT_OK) return bail(st);
@@ -278,7 +298,8 @@ pt_status pt_batch_run(pt_batch *b)
     pt_status st = zero_async(b->ws, b->slots_off, b->stream);
     if (st == PT_OK) st = zero_async(b->d_ctl, b->T_off - b->ctl_off, b->stream);  // ticket and ready/finished words
     if (st != PT_OK) return st;
-    HIPCHK(hipMemcpyAsync(b->d_slots, b->slots.data(), sizeof(JobSlot) * b->njobs, hipMemcpyHostToDevice, b->stream));
+    HIPCHK(hipMemcpyAsync(b->d_slots, b->exec_slots.data(), sizeof(JobSlot) * b->njobs, hipMemcpyHostToDevice,
+                          b->stream));
     HIPCHK(hipMemcpyAsync(b->d_T, b->Tall.data(), sizeof(double) * b->Tall.size(), hipMemcpyHostToDevice, b->stream));
     const JobSlot *slots = b->d_slots;
     int32_t nstatic = b->njobs;
