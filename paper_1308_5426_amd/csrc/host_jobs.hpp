@@ -45,16 +45,17 @@ size_t job_bytes(const pt_job_desc &j, int prec)
 }
 
 // Carve of one job inside a workgroup LDS budget, and which kernel variant
-// runs it: the table in LDS if it fits; else, for q <= 6, in HBM (four or six
-// register rows per flush: 1.7x faster than direct sums on the 16384-site,
-// q = 5 instance), and for larger q direct sums with no table (the HBM flush
-// then updates eight rows, or row by row, per flip: the 256-job batch ran at
-// half the speed of direct sums); int32 tables always keep their table.
+// runs it: the table in LDS if it fits; else, for q <= 7 (at most six stored
+// rows), in HBM (two, four or six register rows per flush: 1.7x faster than
+// direct sums on the 16384-site, q = 5 instance), and for larger q direct sums
+// with no table (an HBM flush of eight rows, or row by row, per flip ran the
+// 256-job batch at half the speed of direct sums); int32 tables always keep
+// their table.
 pt_status job_plan(const pt_job_desc &j, int prec, int budget, int threads, LdsPlan *plan, int32_t *variant)
 {
     const size_t b = static_cast<size_t>(budget);
     const bool in_lds = make_plan(j.L, j.q, j.R, prec, true, kPlLds, b, threads, plan);
-    const int spill = (j.q <= 6 || prec == PT_PREC_I32) ? kPlHbm : kPlDirect;
+    const int spill = (j.q <= 7 || prec == PT_PREC_I32) ? kPlHbm : kPlDirect;
     if (!in_lds && !make_plan(j.L, j.q, j.R, prec, true, spill, b, threads, plan))
         return fail(PT_EINVAL, "job with L = %d, R = %d does not fit an LDS budget of %d B", j.L, j.R, budget);
     *variant = job_variant(plan->place, j.q, plan->j64_in_lds != 0);
