@@ -254,12 +254,14 @@ def run_batch(args):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         shape = b.shape()
+        stats = [b.job_stats(j) for j in range(len(jd))]
         b.close()
         if it >= args.warmup:
             times.append(dt)
         print(f"[batch] step {it} ({'timed' if it >= args.warmup else 'warm-up'}) {dt:.2f} s", file=sys.stderr,
               flush=True)
     el = sum(times)
+    breakdown = batch_breakdown(jd, stats, shape["workgroups"])
     # plain per-instance GPU form: the same jobs one pt_init/pt_run at a time
     k = min(args.plain_sample, len(jd))
     torch.cuda.synchronize()
@@ -283,7 +285,36 @@ def run_batch(args):
                    "accept_fraction": acc / attempts, "shape": shape, "autotuned": bool(args.autotune)},
         "plain_per_instance": {"value": att_plain / dt_plain, "unit": "attempts/s", "jobs_timed": k,
                                "seconds": dt_plain},
+        "breakdown": breakdown,
     }
+
+
+def batch_breakdown(jd, stats, workgroups):
+    """Where a batched launch's time went, from each job's device start and
+    end clocks: the launch span, the fraction of walker slots busy over it,
+    the time spent with fewer than half the slots busy, and each placement's
+    share of jobs, attempts and walker-seconds."""
+    import numpy as np
+
+    t0 = np.array([st["start"] for st in stats])
+    t1 = np.array([st["end"] for st in stats])
+    R = np.array([len(j["T"]) for j in jd], float)
+    att = np.array([j["L"] * len(j["T"]) * j["sweeps"] for j in jd], float)
+    span = float(t1.max() - t0.min())
+    ws = R * (t1 - t0)
+    grid = np.linspace(t0.min(), t1.max(), 2001)
+    busy = np.array([R[(t0 <= t) & (t < t1)].sum() for t in grid]) / workgroups
+    names = {1: "lds", 2: "hbm", 3: "direct"}
+    by = {}
+    for p, name in names.items():
+        m = np.array([st["placement"] == p for st in stats])
+        if m.any():
+            by[name] = {"jobs": int(m.sum()), "attempts_share": float(att[m].sum() / att.sum()),
+                        "walker_seconds_share": float(ws[m].sum() / ws.sum()),
+                        "attempts_per_walker_second": float(att[m].sum() / ws[m].sum())}
+    return {"device_span_s": span, "busy_fraction": float(ws.sum() / (workgroups * span)),
+            "seconds_below_half_busy": float((busy < 0.5).mean() * span),
+            "last_job_start_to_end_s": float(t1.max() - t0.max()), "by_placement": by}
 
 
 def run_serve(args):

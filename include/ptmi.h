@@ -291,6 +291,11 @@ pt_status pt_batch_observables(pt_batch *b, int32_t job, pt_obs *out);
 pt_status pt_batch_get_spins(pt_batch *b, int32_t job, uint8_t *spins_out, int32_t *perm_out);
 /* Workgroups used by the launch and threads per workgroup (for reporting). */
 pt_status pt_batch_shape(pt_batch *b, int32_t *workgroups, int32_t *threads, int32_t *lds_bytes);
+/* Placement of job `job`'s field table (PT_PLACE_LDS, _HBM or _DIRECT), and,
+ * after pt_batch_run (synchronising), the device wall clock in seconds when
+ * the job's set-up began and when its last walker finished (a clock common to
+ * every job of the launch).  Any pointer may be NULL. */
+pt_status pt_batch_job_stats(pt_batch *b, int32_t job, int32_t *placement, double *start_s, double *end_s);
 pt_status pt_batch_free(pt_batch *b);
 
 /* ------------------------------------------------------------------------ */

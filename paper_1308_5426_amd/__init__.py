@@ -85,7 +85,7 @@ EXPORTS = [
     "pt_observables", "pt_get_spins", "pt_get_jstar", "pt_get_series", "pt_get_events",
     "pt_get_plan", "pt_get_phase_counters", "pt_reset_stats", "pt_synchronize", "pt_save", "pt_load", "pt_free", "pt_last_error",
     "pt_batch_workspace_size", "pt_batch_create", "pt_batch_run", "pt_batch_observables",
-    "pt_batch_get_spins", "pt_batch_shape", "pt_batch_free",
+    "pt_batch_get_spins", "pt_batch_shape", "pt_batch_job_stats", "pt_batch_free",
     "pt_server_workspace_size", "pt_server_start", "pt_server_submit", "pt_server_poll", "pt_server_wait", "pt_server_times",
     "pt_server_get_spins", "pt_server_cancel", "pt_server_stop", "pt_run_static",
 ]
@@ -137,6 +137,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.pt_batch_observables.argtypes = [_P, i32, OB]
     L.pt_batch_get_spins.argtypes = [_P, i32, _P, _P]
     L.pt_batch_shape.argtypes = [_P, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.pt_batch_job_stats.argtypes = [_P, i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]
     L.pt_batch_free.argtypes = [_P]
     L.pt_server_workspace_size.argtypes = [ctypes.c_size_t, i32, ctypes.POINTER(ctypes.c_size_t)]
     L.pt_server_start.argtypes = [pp, ctypes.c_size_t, i32, OP]
@@ -418,6 +420,13 @@ class Batch:
         w, t, l = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         _check(self._lib.pt_batch_shape(self._h, ctypes.byref(w), ctypes.byref(t), ctypes.byref(l)))
         return dict(workgroups=w.value, threads=t.value, lds_bytes=l.value)
+
+    def job_stats(self, j) -> dict:
+        """Placement of job j's table (PLACE_*) and, after run(), the device
+        wall clock (s) when its set-up began and when its last walker ended."""
+        p, t0, t1 = ctypes.c_int32(), ctypes.c_double(), ctypes.c_double()
+        _check(self._lib.pt_batch_job_stats(self._h, int(j), ctypes.byref(p), ctypes.byref(t0), ctypes.byref(t1)))
+        return dict(placement=p.value, start=t0.value, end=t1.value)
 
     def observables(self, j) -> dict:
         R = self.R[j]

@@ -36,7 +36,7 @@ pt_status validate_job(const pt_job_desc &j)
 size_t server_bytes(size_t arena_bytes, int32_t max_jobs)
 {
     return Layout::up(arena_bytes) + Layout::up(sizeof(JobControl)) +
-           Layout::up(sizeof(unsigned long long) * 2 * static_cast<size_t>(max_jobs));
+           Layout::up(sizeof(unsigned long long) * kJcWords * static_cast<size_t>(max_jobs));
 }
 
 size_t job_bytes(const pt_job_desc &j, int prec)
@@ -148,7 +148,7 @@ struct pt_batch {
     std::vector<pt_job_desc> jobs;
     JobSlot *d_slots = nullptr;
     JobControl *d_ctl = nullptr;
-    unsigned long long *d_jc = nullptr;  // [njobs][2] ready / finished words
+    unsigned long long *d_jc = nullptr;  // [njobs][kJcWords] ready / finished words, clocks
     double *d_T = nullptr;
     std::vector<double> Tall;
     size_t slots_off = 0, ctl_off = 0, jc_off = 0, T_off = 0, total = 0;
@@ -175,7 +175,7 @@ pt_status batch_layout(const pt_job_desc *jobs, int32_t n, const pt_options &o, 
     b->ctl_off = off;
     off += Layout::up(sizeof(JobControl));
     b->jc_off = off;
-    off += Layout::up(sizeof(unsigned long long) * 2 * static_cast<size_t>(n));
+    off += Layout::up(sizeof(unsigned long long) * kJcWords * static_cast<size_t>(n));
     b->T_off = off;
     off += Layout::up(sizeof(double) * nT);
     b->total = off;
@@ -279,7 +279,7 @@ pt_status pt_batch_create(pt_batch **out, const pt_job_desc *jobs, int32_t njobs
     for (int k = 0; k < njobs; ++k) {
         const int j = order[k];
         job_slot(b->slots[j], jobs[j], b->prec, b->ws + b->job_off[j], b->d_T + T_at[j], plans[j], variants[j], wbase,
-                 b->d_jc + 2 * static_cast<size_t>(j));
+                 b->d_jc + kJcWords * static_cast<size_t>(j));
         b->exec_slots[k] = b->slots[j];
         wbase += jobs[j].R;
     }
@@ -344,6 +344,26 @@ pt_status pt_batch_shape(pt_batch *b, int32_t *wgs, int32_t *threads, int32_t *l
     return PT_OK;
 }
 
+pt_status pt_batch_job_stats(pt_batch *b, int32_t job, int32_t *placement, double *start_s, double *end_s)
+{
+    if (!b) return fail(PT_EINVAL, "null batch");
+    if (job < 0 || job >= b->njobs) return fail(PT_EINVAL, "job index out of range");
+    if (placement) *placement = b->slots[job].plan.place;
+    if (!start_s && !end_s) return PT_OK;
+    if (!b->ran) return fail(PT_ESTATE, "batch has not run");
+    HIPCHK(hipStreamSynchronize(b->stream));
+    unsigned long long w[kJcWords];
+    HIPCHK(hipMemcpy(w, b->d_jc + kJcWords * static_cast<size_t>(job), sizeof w, hipMemcpyDeviceToHost));
+    int dev = 0, khz = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    if (khz <= 0) return fail(PT_EDEVICE, "no device wall-clock rate");
+    const double per_s = 1e3 * khz;
+    if (start_s) *start_s = static_cast<double>(w[2]) / per_s;
+    if (end_s) *end_s = static_cast<double>(w[3]) / per_s;
+    return PT_OK;
+}
+
 pt_status pt_batch_free(pt_batch *b)
 {
     if (!b) return fail(PT_EINVAL, "null batch");
@@ -377,7 +397,7 @@ struct pt_server {
     bool own_mem = false;
     size_t ctl_off = 0, jc_off = 0;
     JobControl *d_ctl = nullptr;
-    unsigned long long *d_jc = nullptr;  // [max_jobs][2]
+    unsigned long long *d_jc = nullptr;  // [max_jobs][kJcWords]
     int32_t *h_ctl = nullptr;       // pinned: [0] published, [1] stop
     int32_t *h_done = nullptr;      // pinned: [max_jobs]
     JobSlot *h_slots = nullptr;     // pinned: [max_jobs] job table read by the running kernel
@@ -459,7 +479,7 @@ bool server_admit(pt_server *s)
         double *Th = s->h_T + static_cast<size_t>(J.slot) * kServerMaxR;
         std::memcpy(Th, J.T.data(), sizeof(double) * J.desc.R);
         job_slot(s->h_slots[J.slot], J.desc, s->prec, s->mem + off, Th, plan, variant, s->wbase,
-                 s->d_jc + 2 * static_cast<size_t>(J.slot));
+                 s->d_jc + kJcWords * static_cast<size_t>(J.slot));
         s->wbase += J.desc.R;
         s->inflight += J.desc.R;
         s->published += 1;

@@ -38,11 +38,17 @@ __host__ __device__ inline int32_t job_variant(int place, int q, bool j64_in_lds
     return static_cast<int32_t>(place) | (qt << kVarQtShift) | (j64_in_lds ? kVarJ64Lds : 0);
 }
 
+// Per-job device words: [0] couplings ready, [1] walkers finished, [2] the
+// device wall clock when walker 0 began the set-up, [3] when the last walker
+// finished (wall_clock64 ticks).
+constexpr int kJcWords = 4;
+
 struct alignas(256) JobSlot {
     Inst inst;
     LdsPlan plan;      // carve of this job inside the launch's LDS budget
     const double *T;   // [R] ascending temperatures (device or pinned host memory)
-    unsigned long long *jc;  // [2] couplings ready, walkers finished (device memory, zero at launch)
+    unsigned long long *jc;  // [kJcWords] couplings ready, walkers finished, start and end clocks (device
+                             // memory, zero at launch)
     double sigma;
     int64_t sweeps;
     int32_t xevery;
@@ -71,6 +77,7 @@ __device__ __forceinline__ void run_job_walker(const JobSlot &S, int w, unsigned
     unsigned long long *const jc = S.jc;
     const int tid = threadIdx.x, L = P.L, R = P.R;
     if (w == 0) {
+        if (tid == 0) jc[2] = wall_clock64();
         // the job's counters (the arena block may have held an earlier job),
         // couplings, error bounds, ladder and zeroed accumulators
         for (int k = tid; k < kCtrN; k += blockDim.x) P.ctr[k] = 0ull;
@@ -140,9 +147,12 @@ __device__ __forceinline__ void run_job_walker(const JobSlot &S, int w, unsigned
         if (!ok) atomicOr(&P.ctr[kCtrError], kErrBarrierTimeout);
         __threadfence_system();
         const unsigned long long d = __hip_atomic_fetch_add(&jc[1], 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (done_flag && d == static_cast<unsigned long long>(R) - 1ull) {
-            __threadfence_system();
-            __hip_atomic_store(done_flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        if (d == static_cast<unsigned long long>(R) - 1ull) {
+            jc[3] = wall_clock64();
+            if (done_flag) {
+                __threadfence_system();
+                __hip_atomic_store(done_flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
         }
     }
     __syncthreads();

@@ -73,6 +73,7 @@ def test_host_only_calls():
     assert b"ascending" in lib.pt_last_error()
     assert lib.pt_sweep(None, 1) == pkg.PT_EINVAL
     assert lib.pt_server_cancel(None, 0) == pkg.PT_EINVAL
+    assert lib.pt_batch_job_stats(None, 0, None, None, None) == pkg.PT_EINVAL
 
 
 def test_probe_library_exports():

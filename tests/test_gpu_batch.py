@@ -114,6 +114,29 @@ def test_batch_equals_single_instance(pkg):
     b.close()
 
 
+def test_batch_job_stats(pkg):
+    """Each job's placement as planned and its device start and end clocks:
+    start before end, every job inside one launch."""
+    from workloads import geometric_ladder
+
+    T = geometric_ladder(0.3, 3.0, 8)
+    jobs = [dict(L=64 + 32 * j, q=3, sigma=0.5, T=T, seed=40 + j, sweeps=20 + 30 * j, exchange_every=1, init=0)
+            for j in range(6)]
+    b = pkg.Batch(jobs)
+    with pytest.raises(pkg.PTError):
+        b.job_stats(0)  # no clocks before the launch
+    b.run()
+    st = [b.job_stats(j) for j in range(len(jobs))]
+    assert all(s["placement"] == pkg.PLACE_LDS for s in st)
+    t0 = np.array([s["start"] for s in st])
+    t1 = np.array([s["end"] for s in st])
+    assert (t0 < t1).all()
+    assert t1.max() - t0.min() < 60.0
+    with pytest.raises(pkg.PTError):
+        b.job_stats(len(jobs))
+    b.close()
+
+
 def test_batch_more_walkers_than_workgroups(pkg, orc):
     """Far more walkers than resident workgroups: jobs are taken in turn."""
     from workloads import geometric_ladder
