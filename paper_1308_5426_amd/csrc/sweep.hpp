@@ -825,18 +825,24 @@ __device__ __forceinline__ double direct_dE_window(const Walker<F> &W, int L, in
     const int per = (kWave + nw - 1) / nw;
     const int g0 = wv * per, g1 = min(kWave, g0 + per);
     double mine = 0.0;
-    for (int g = g0; g < g1; ++g) {
-        const int ig = rl_i(i, g), ag = rl_i(a, g), bg = rl_i(b, g);
-        double part = 0.0;
+    // two attempts per pass over the spins (each spin read once for both)
+    for (int g = g0; g < g1; g += 2) {
+        const int h = min(g + 1, g1 - 1);  // an odd share repeats its last attempt
+        const int i0 = rl_i(i, g), a0 = rl_i(a, g), b0 = rl_i(b, g);
+        const int i1 = rl_i(i, h), a1 = rl_i(a, h), b1 = rl_i(b, h);
+        double p0 = 0.0, p1 = 0.0;
         for (int j = lane; j < L; j += kWave) {
             const int s = W.sp[j];
-            int d = j - ig;
-            d += d < 0 ? L : 0;
-            const double jv = W.J64[d];
-            part += s == ag ? jv : (s == bg ? -jv : 0.0);
+            int d0 = j - i0, d1 = j - i1;
+            d0 += d0 < 0 ? L : 0;
+            d1 += d1 < 0 ? L : 0;
+            const double v0 = W.J64[d0], v1 = W.J64[d1];
+            p0 += s == a0 ? v0 : (s == b0 ? -v0 : 0.0);
+            p1 += s == a1 ? v1 : (s == b1 ? -v1 : 0.0);
         }
-        const double tot = wave_sum(part);
-        mine = lane == g ? tot : mine;
+        const double t0 = wave_sum(p0), t1 = wave_sum(p1);
+        mine = lane == g ? t0 : mine;
+        mine = lane == h ? t1 : mine;
     }
     if (nw == 1) return mine;
     double *xp = W.xpart + pbuf * nw * kWave;
