@@ -578,7 +578,8 @@ def main():
         out["batched"] = {"metric": b["metric"], "value": b["value"], "unit": b["unit"],
                           "seconds": b["ms_per_step"] / 1e3, "config": b["config"],
                           "plain_per_instance": b["plain_per_instance"],
-                          "batched_over_plain": b["value"] / b["plain_per_instance"]["value"]}
+                          "batched_over_plain": b["value"] / b["plain_per_instance"]["value"],
+                          "breakdown": b["breakdown"]}
     print(json.dumps(out), flush=True)
 
 
