@@ -88,15 +88,15 @@ def test_probe_library_exports():
         assert hasattr(lib, name)
 
 
-def _checkpoint(L, q, R, spins, perm, prec=0, init=0):
+def _checkpoint(L, q, R, spins, perm, prec=0, init=0, T=None, sigma=0.5):
     """A checkpoint buffer in the library's layout: header, T, spins (0-based),
     perm, six moment sums and four counter arrays per slot."""
     import struct
 
     import numpy as np
 
-    hdr = struct.pack("<IIiiiiiiQdqqq", 0x50544D49, 1, L, q, R, prec, init, 0, 1234, 0.5, 0, 0, 0)
-    T = np.linspace(1.0, 2.0, R).astype("<f8").tobytes()
+    hdr = struct.pack("<IIiiiiiiQdqqq", 0x50544D49, 1, L, q, R, prec, init, 0, 1234, sigma, 0, 0, 0)
+    T = (np.linspace(1.0, 2.0, R) if T is None else np.asarray(T, float)).astype("<f8").tobytes()
     body = (np.asarray(spins, np.uint8).tobytes() + np.asarray(perm, "<i4").tobytes()
             + np.zeros(6 * R, "<f8").tobytes() + np.zeros(4 * R, "<i8").tobytes())
     return hdr + T + body
@@ -140,6 +140,40 @@ def test_load_rejects_corrupt_checkpoint(case):
         return
     assert st == pkg.PT_EINVAL, lib.pt_last_error()
     assert not ctx.value
+
+
+@pytest.mark.parametrize("bad", ["T_nan", "T_inf", "T_zero", "sigma_nan", "sigma_inf"])
+def test_non_finite_inputs_are_refused_on_the_host(bad):
+    """NaN or infinite temperatures or sigma, given directly or inside a
+    checkpoint, are refused with PT_EINVAL before any device call."""
+    import numpy as np
+
+    import paper_1308_5426_amd as pkg
+
+    if not os.path.exists(pkg.LIB_PATH):
+        pytest.skip("library not built")
+    lib = pkg.load_library()
+    L, q, R = 16, 3, 4
+    T = np.linspace(1.0, 2.0, R)
+    sigma = 0.5
+    if bad == "T_nan":
+        T[2] = np.nan
+    elif bad == "T_inf":
+        T[3] = np.inf
+    elif bad == "T_zero":
+        T[0] = 0.0
+    elif bad == "sigma_nan":
+        sigma = float("nan")
+    else:
+        sigma = float("inf")
+    ctx = ctypes.c_void_p()
+    Tc = np.ascontiguousarray(T)
+    st = lib.pt_init(ctypes.byref(ctx), L, q, ctypes.c_double(sigma), Tc.ctypes.data_as(ctypes.c_void_p), R, 1, None)
+    assert st == pkg.PT_EINVAL and not ctx.value, lib.pt_last_error()
+    blob = _checkpoint(L, q, R, np.zeros((R, L), np.uint8), np.arange(R), T=T, sigma=sigma)
+    raw = ctypes.create_string_buffer(blob, len(blob))
+    st = lib.pt_load(ctypes.byref(ctx), ctypes.cast(raw, ctypes.c_void_p), len(blob), None)
+    assert st == pkg.PT_EINVAL and not ctx.value, lib.pt_last_error()
 
 
 def test_run_static_rejects_on_the_host():
